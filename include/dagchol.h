@@ -1,0 +1,274 @@
+/*
+ * dagchol: task-DAG tiled Cholesky factorisation and solve on one MI355X.
+ *
+ * The programming model is the one of the paper's Section 2: data buffers are
+ * registered as handles, tasks are submitted asynchronously with an access
+ * mode (read-only, write-only, read-write) for every buffer argument, and the
+ * dependency graph of the tasks follows from those modes plus the order of
+ * submission; a wait call blocks until every submitted task has completed.
+ * Section 3.2 gives the mode rule for parameters (unqualified pointer:
+ * read-write, const pointer: read-only, output attribute: write-only, scalars
+ * by value); Section 3.4 the register/unregister/acquire operations; Section
+ * 5.1 the partitioning of a registered matrix into sub-matrix handles, the
+ * idiom of tiled Cholesky; Section 5.3 task priorities as scheduling hints.
+ *
+ * The tasks run on the GPU inside one persistent executor kernel that pops
+ * ready work from device-side queues as dependency counters reach zero.
+ *
+ * Conventions for every entry point
+ * ---------------------------------
+ *  - Return value: 0 on success, a negative errno on failure, in which case
+ *    the call had no effect:
+ *      -EINVAL     bad argument: arity or access mode not matching the task
+ *                  kind's signature, dtype or shape mismatch, null pointer;
+ *      -ENOENT     unknown or unregistered handle or pointer (the paper's
+ *                  generated task body rejects unregistered pointers);
+ *      -EBUSY      a partitioned matrix used as a whole, or a handle still
+ *                  referenced by pending tasks;
+ *      -ENOMEM     host or device memory exhausted, or a capacity exceeded;
+ *      -ENODEV     execution requested from a host-only runtime;
+ *      -ETIMEDOUT  the executor's watchdog fired;
+ *      -EIO        a HIP runtime call failed.
+ *    The library never aborts the process (unlike the paper's generated
+ *    code, which calls abort on these errors).
+ *  - Numerical breakdown is not an error code: a factorisation of a matrix
+ *    that is not numerically positive definite completes, and dc_get_info
+ *    reports the 1-based global column of the first non-positive pivot
+ *    (LAPACK convention); tasks that depend on the failed diagonal factor
+ *    are skipped and the matrix contents are then unspecified.
+ *  - Ownership: device buffers belong to the caller.  The library borrows
+ *    them from register to unregister; they must stay allocated until the
+ *    handle is unregistered (Section 3.4 warns that storage reclaimed before
+ *    tasks complete is an error).  Handles, task descriptors and executor
+ *    state belong to the runtime.  Scalar task arguments are copied at
+ *    submission.
+ *  - Layout: matrices are row-major with a leading dimension `ld` (elements
+ *    between consecutive rows); only the lower triangle (row >= column) of a
+ *    symmetric matrix is read or written.
+ *  - Ordering: results equal those of executing the tasks one after another
+ *    in submission order (the paper's "valid sequential program").
+ *  - Threading: a runtime is not thread-safe; use one runtime per host
+ *    thread.  All work is issued on the runtime's HIP stream.
+ */
+#ifndef DAGCHOL_H
+#define DAGCHOL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dc_runtime dc_runtime;
+
+/* Opaque handle; 0 is the null handle (like a failed data lookup). */
+typedef int64_t dc_handle;
+
+/* Access modes; read-write is the union of read and write. */
+typedef enum { DC_R = 1, DC_W = 2, DC_RW = 3 } dc_mode;
+
+typedef enum { DC_F64 = 0, DC_F32 = 1, DC_BF16 = 2 } dc_dtype;
+
+/*
+ * Task kinds and their buffer signatures (handles in this order):
+ *   DC_POTRF      (D:RW)            D = L L^T in place, lower, one diagonal
+ *                                   tile; scalar: int64 global row offset of
+ *                                   D (for the info column), optional.
+ *   DC_TRSM       (L:R, X:RW)       X <- X L^{-T}, L lower non-unit.
+ *   DC_SYRK       (X:R, C:RW)       lower(C) <- lower(C) - X X^T.
+ *   DC_GEMM       (X:R, Y:R, C:RW)  C <- C - X Y^T.
+ *   DC_TRSM_L     (L:R, B:RW)       B <- L^{-1} B (forward substitution).
+ *   DC_TRSM_LT    (L:R, B:RW)       B <- L^{-T} B (backward substitution).
+ *   DC_GEMM_RHS_N (L:R, Y:R, B:RW)  B <- B - L Y.
+ *   DC_GEMM_RHS_T (L:R, Y:R, B:RW)  B <- B - L^T Y.
+ *   DC_SCAL       (X:RW)            x <- factor * x, float vector; scalar:
+ *                                   one float (the paper's scale_vector).
+ *   DC_CAST       (S:R, D:W)        D <- S converted to D's dtype (round to
+ *                                   nearest even), same shape.
+ *   DC_RESID      (A:R, X:R, B:R, R:W)  R <- B - A X, A symmetric given by
+ *                                   its lower triangle, FP64.
+ *   DC_AXPY       (D:R, X:RW)       X <- X + D, FP64 matrices of one shape.
+ * Tiles may be FP64, or (mixed precision) FP32 for TRSM, SYRK and GEMM
+ * inputs and BF16 for SYRK/GEMM inputs, as the dtypes of the handles say.
+ */
+typedef enum {
+  DC_POTRF = 0, DC_TRSM = 1, DC_SYRK = 2, DC_GEMM = 3,
+  DC_TRSM_L = 4, DC_GEMM_RHS_N = 5, DC_TRSM_LT = 6, DC_GEMM_RHS_T = 7,
+  DC_SCAL = 8, DC_CAST = 9, DC_RESID = 10, DC_AXPY = 11,
+  DC_NUM_KINDS = 12
+} dc_kind;
+
+typedef struct {
+  int device;            /* HIP device ordinal; -1: host-only runtime that
+                            builds and inspects graphs but cannot execute */
+  void *stream;          /* hipStream_t to issue work on; NULL: a stream the
+                            runtime creates */
+  int workers;           /* persistent workgroups; 0: one per CU times the
+                            kernel's occupancy */
+  int64_t watchdog_ms;   /* executor gives up after this long without
+                            progress; 0: 60000 */
+  int trace;             /* nonzero: record a per-task trace at every wait */
+} dc_config;
+
+/* Fills cfg with defaults (device 0, own stream, automatic workers). */
+void dc_config_default(dc_config *cfg);
+
+/* Creates a runtime.  Errors: -EINVAL (null pointer), -EIO (HIP failure,
+ * e.g. no such device), -ENOMEM. */
+int dc_init(dc_runtime **rt, const dc_config *cfg);
+
+/* Waits for pending work, frees runtime state (never user buffers). */
+int dc_shutdown(dc_runtime *rt);
+
+/* Registers a vector of nx elements at device address ptr (Section 2's
+ * vector registration).  Errors: -EINVAL, -EBUSY (ptr already registered). */
+int dc_vector_register(dc_runtime *rt, dc_handle *out, void *ptr, int64_t nx,
+                       dc_dtype dtype);
+
+/* Registers a rows x cols row-major matrix with leading dimension ld >= cols
+ * (Section 5.1's matrix).  Errors: -EINVAL, -EBUSY. */
+int dc_matrix_register(dc_runtime *rt, dc_handle *out, void *ptr, int64_t rows,
+                       int64_t cols, int64_t ld, dc_dtype dtype);
+
+/* Partitions a registered matrix into ceil(rows/tile) x ceil(cols/tile)
+ * sub-matrix handles (Section 5.1's filters): tile (I, J) starts at element
+ * (I*tile, J*tile), keeps the parent's ld, and the last row/column of tiles
+ * is ragged when tile does not divide the size.  tiles_out receives the
+ * handles row-major (I * tcols + J) and must hold trows*tcols entries.
+ * While partitioned, the parent cannot be used in tasks (-EBUSY).
+ * Errors: -ENOENT, -EINVAL, -EBUSY (already partitioned or has pending
+ * tasks). */
+int dc_matrix_partition(dc_runtime *rt, dc_handle m, int64_t tile,
+                        dc_handle *tiles_out);
+
+/* Gathers the tiles back: waits for their pending tasks, drops the tile
+ * handles.  Errors: -ENOENT, -EINVAL (not partitioned). */
+int dc_matrix_unpartition(dc_runtime *rt, dc_handle m);
+
+/* Number of tile rows and columns of a partitioned matrix. */
+int dc_matrix_tiles(dc_runtime *rt, dc_handle m, int64_t *trows, int64_t *tcols);
+
+/* Finds the top-level handle registered at ptr; *out = 0 and -ENOENT when
+ * there is none (the lookup of the paper's generated task body). */
+int dc_handle_lookup(dc_runtime *rt, const void *ptr, dc_handle *out);
+
+/* Submits one task.  bufs/modes: nbuf handles with their access modes, in
+ * the order of the kind's signature above; the modes must equal the
+ * signature's (a W where RW is declared is accepted: W is RW without the
+ * read).  cl_args: packed scalars, copied (at most 64 bytes).  priority: 0
+ * is the most urgent; larger values run later when both are ready
+ * (Section 5.3's hint); values above 3 are clamped.
+ * Dependencies: a task that reads a handle waits for its last writer; a
+ * task that writes a handle waits for the last writer and every reader since
+ * (Section 2).  Sub-matrix handles of one partition are independent data.
+ * Errors: -EINVAL, -ENOENT, -EBUSY, -ENOMEM. */
+int dc_task_submit(dc_runtime *rt, dc_kind kind, int nbuf, const dc_handle *bufs,
+                   const dc_mode *modes, const void *cl_args, size_t cl_args_size,
+                   int priority);
+
+/* Starts executing every submitted task (one persistent kernel launch on the
+ * runtime's stream) without waiting.  Submissions after a flush form a new
+ * graph that runs after the flushed one. */
+int dc_flush(dc_runtime *rt);
+
+/* Blocks until every submitted task has completed (Sections 2 and 3.3).
+ * Errors: -ETIMEDOUT (watchdog), -EIO, -ENODEV (host-only runtime with
+ * pending tasks; the tasks are discarded). */
+int dc_wait_all(dc_runtime *rt);
+
+/* Makes a handle's data valid for the host to access (Section 3.4's
+ * acquire): waits for the tasks that write it (mode R) or that touch it
+ * (mode W/RW).  dc_release ends the access. */
+int dc_acquire(dc_runtime *rt, dc_handle h, dc_mode mode);
+int dc_release(dc_runtime *rt, dc_handle h);
+
+/* Waits for the tasks that touch h, then forgets it (and its tiles). */
+int dc_unregister(dc_runtime *rt, dc_handle h);
+
+/* Numerical status of a matrix handle after its tasks completed: 0, or the
+ * 1-based global column of the first non-positive pivot. */
+int dc_get_info(dc_runtime *rt, dc_handle m, int64_t *info);
+
+/* Launch-path self test: fills the n int64 values at device address ptr
+ * with 2 i + 1 on `stream` (a hipStream_t, NULL for the default stream)
+ * and waits.  Errors: -EINVAL, -EIO. */
+int dc_selftest(void *ptr, int64_t n, void *stream);
+
+/* Text for a return code. */
+const char *dc_strerror(int err);
+
+/* Detail of the last -EIO on the calling thread (the failing HIP call and
+ * its error name), or an empty string. */
+const char *dc_last_error(void);
+
+/* ---------------------------------------------------------------- graphs */
+
+/* Inspection of the graph submitted since the last flush/wait (also on a
+ * host-only runtime): number of tasks, of dependency edges, of edges present
+ * only because of a write-after-read, and the task count of the longest
+ * dependency chain. */
+typedef struct {
+  int64_t ntasks, nedges, nwar_edges, critical_path, nunits;
+} dc_graph_stats;
+int dc_graph_stats_get(dc_runtime *rt, dc_graph_stats *out);
+
+/* Predecessors of pending task t (0-based submission index): writes up to
+ * cap task indices, *count receives the total. */
+int dc_graph_preds(dc_runtime *rt, int64_t t, int64_t *preds, int64_t cap,
+                   int64_t *count);
+
+/* Per-task trace of the last executed graph (config.trace != 0): for task t,
+ * start and end times (ns, device clock), the workgroup that finished it and
+ * its kind.  Errors: -ENOENT (no trace). */
+int dc_trace_get(dc_runtime *rt, int64_t t, int64_t *start_ns, int64_t *end_ns,
+                 int32_t *worker, int32_t *kind);
+
+/* Diagnostics of the last executor launch: host time spent laying out the
+ * graph (ms), work units and persistent workgroups launched.  Any output
+ * pointer may be NULL. */
+int dc_last_launch(dc_runtime *rt, double *build_ms, int64_t *units, int32_t *workers);
+
+/* ------------------------------------------------ high-level operations */
+
+/* Each of these only submits tasks through dc_task_submit (the matrix must
+ * be registered and not partitioned; it is partitioned with the given tile
+ * size for the duration of the call) and then waits.
+ *
+ * dc_potrf: tiled right-looking Cholesky of the lower triangle of A in
+ * place, in FP64: for k, POTRF(k); TRSM(i,k) for i>k; SYRK(i,k) and
+ * GEMM(i,j,k) for k<j<i.  Result: dc_get_info(A). */
+int dc_potrf(dc_runtime *rt, dc_handle A, int64_t tile);
+
+/* dc_potrs: solves L L^T X = B in place in B (n x r, FP64) with the factor
+ * in the lower triangle of L: forward sweep TRSM_L/GEMM_RHS_N, backward
+ * sweep TRSM_LT/GEMM_RHS_T. */
+int dc_potrs(dc_runtime *rt, dc_handle L, dc_handle B, int64_t tile);
+
+/* Mixed-precision solve with FP64-residual iterative refinement.  A (n x n
+ * FP64, lower triangle) is left unchanged.  upd selects the precision of the
+ * SYRK/GEMM updates (DC_F64, DC_F32 or DC_BF16); the diagonal POTRF tasks
+ * stay FP64 and off-diagonal factor tiles are stored in FP32 when upd is not
+ * DC_F64.  x0 = solve(b); then r = b - A x (FP64), d = solve(r), x += d
+ * until ||d||_inf <= tol ||x||_inf for every column, stagnation
+ * (||d_i|| > 0.5 ||d_{i-1}||) or maxit steps.  If the factor breaks down or
+ * refinement does not converge, the next wider precision is used (BF16 ->
+ * FP32 -> FP64).  B and X are n x r FP64; X receives the solution. */
+typedef struct {
+  int iterations;        /* refinement steps of the precision that was kept */
+  int converged;         /* 1 if the stopping test was met */
+  int final_prec;        /* dc_dtype actually used for the updates */
+  int fallbacks;         /* precision changes made */
+  double last_update;    /* ||d||_inf / ||x||_inf at the last step */
+  double factor_ms;      /* device time of the last factorisation */
+  double refine_ms;      /* device time of the solves and refinement */
+} dc_ir_report;
+int dc_posv_ir(dc_runtime *rt, dc_handle A, dc_handle B, dc_handle X,
+               int64_t tile, dc_dtype upd, double tol, int maxit,
+               dc_ir_report *rep);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DAGCHOL_H */

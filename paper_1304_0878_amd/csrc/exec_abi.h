@@ -1,0 +1,75 @@
+// Internal ABI between the host runtime and the device executor.
+// Not part of the public interface (include/dagchol.h).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dcx {
+
+// Task kinds: the same numbering as dc_kind in the public header.
+enum Kind : int32_t {
+  K_POTRF = 0, K_TRSM = 1, K_SYRK = 2, K_GEMM = 3,
+  K_TRSM_L = 4, K_GEMM_RHS_N = 5, K_TRSM_LT = 6, K_GEMM_RHS_T = 7,
+  K_SCAL = 8, K_CAST = 9, K_RESID = 10, K_AXPY = 11,
+  K_NUM = 12
+};
+
+enum DType : int32_t { T_F64 = 0, T_F32 = 1, T_BF16 = 2 };
+
+// Output sub-block edge of one GEMM/SYRK work unit.
+constexpr int GEMM_UNIT = 128;
+// Rows of the solve/residual/cast work units.
+constexpr int ROW_UNIT = 64;
+// Column block of POTRF and TRSM.
+constexpr int PANEL = 16;
+// Largest tile edge the POTRF and TRSM units accept.
+constexpr int MAX_TILE = 1024;
+// LDS budget (doubles) of the TRSM row panel.
+constexpr int TRSM_LDS_DOUBLES = 16896;
+
+// Rows of X one TRSM unit keeps in LDS for a tile of width nb.
+__host__ __device__ inline int trsm_rows(int nb) {
+  int r = 32;
+  while (r > 1 && r * (nb + 1) > TRSM_LDS_DOUBLES) r >>= 1;
+  return r;
+}
+
+// One task, as the executor reads it (128 bytes).
+struct TaskDesc {
+  int32_t kind;
+  int32_t nunits;
+  int32_t m, n, k;        // extents (meaning per kind, see device.hip)
+  int32_t ta, tb, tc;     // dtypes of buffers a, b, c
+  int32_t matrix;         // numerical-status slot, -1 if none
+  int32_t flags;
+  int64_t lda, ldb, ldc, ldd;
+  void *a, *b, *c, *d;
+  int64_t row0;           // global row offset of a POTRF tile
+  double alpha;           // scalar argument
+  int64_t pad0;
+};
+static_assert(sizeof(TaskDesc) == 128, "descriptor size");
+
+constexpr int MAX_LANES = 4;
+
+// Device-side view of one level launch.
+struct LevelArgs {
+  const TaskDesc *desc;
+  const uint64_t *items;   // (task << 32 | unit), levels concatenated
+  int64_t begin;           // first item of this level
+  int64_t count;           // items in this level
+  unsigned long long *counter;  // next item to take (zero before the launch)
+  int32_t *failed;         // per matrix: nonzero after a breakdown
+  int64_t *info;           // per matrix: 0 or 1-based breakdown column
+  int64_t *trace;          // optional: per task start, end (clock ticks), worker
+};
+
+}  // namespace dcx
+
+// Launches one level on `stream` (a hipStream_t); returns a hipError_t value.
+extern "C++" int dcx_launch_level(const dcx::LevelArgs &args, int workers, size_t lds_bytes,
+                                  void *stream);
+// Allows the level kernel its largest dynamic LDS size.
+extern "C++" int dcx_level_setup(void);
+// Workgroups per CU the level kernel keeps resident with lds_bytes of LDS.
+extern "C++" int dcx_level_occupancy(size_t lds_bytes, int *blocks_per_cu);

@@ -1,0 +1,139 @@
+// High-level operations of dagchol.  Each one only partitions registered
+// matrices and submits tile tasks through dc_task_submit, then waits: they
+// are ordinary clients of the task interface (Section 2 of the paper), the
+// tiled Cholesky being the partitioning idiom of its Section 5.1.
+#include <errno.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <vector>
+
+#include "../../include/dagchol.h"
+#include "runtime_internal.h"
+
+namespace {
+
+struct Tiles {
+  dc_runtime *rt = nullptr;
+  dc_handle m = 0;
+  int64_t tr = 0, tc = 0;
+  std::vector<dc_handle> ids;
+  bool active = false;
+  int open(dc_runtime *r, dc_handle h, int64_t tile) {
+    rt = r;
+    m = h;
+    Handle *p = rt->get(h);
+    if (!p) return -ENOENT;
+    tr = (p->rows + tile - 1) / tile;
+    tc = (p->cols + tile - 1) / tile;
+    ids.assign(tr * tc, 0);
+    int e = dc_matrix_partition(rt, h, tile, ids.data());
+    active = e == 0;
+    return e;
+  }
+  dc_handle at(int64_t i, int64_t j) const { return ids[i * tc + j]; }
+  ~Tiles() {
+    if (active) dc_matrix_unpartition(rt, m);
+  }
+};
+
+int submit1(dc_runtime *rt, dc_kind k, dc_handle a, dc_mode ma, int prio,
+            const void *cl = nullptr, size_t cls = 0) {
+  dc_handle b[1] = {a};
+  dc_mode m[1] = {ma};
+  return dc_task_submit(rt, k, 1, b, m, cl, cls, prio);
+}
+int submit2(dc_runtime *rt, dc_kind k, dc_handle a, dc_mode ma, dc_handle c, dc_mode mc,
+            int prio) {
+  dc_handle b[2] = {a, c};
+  dc_mode m[2] = {ma, mc};
+  return dc_task_submit(rt, k, 2, b, m, nullptr, 0, prio);
+}
+int submit3(dc_runtime *rt, dc_kind k, dc_handle a, dc_mode ma, dc_handle c, dc_mode mc,
+            dc_handle e, dc_mode me, int prio) {
+  dc_handle b[3] = {a, c, e};
+  dc_mode m[3] = {ma, mc, me};
+  return dc_task_submit(rt, k, 3, b, m, nullptr, 0, prio);
+}
+
+#define TRY(x) do { int e_ = (x); if (e_) return e_; } while (0)
+
+}  // namespace
+
+// Right-looking tiled factorisation on partitioned tiles (submission only).
+// Priorities (Section 5.3's hints): the diagonal factor, the panel TRSMs and
+// the updates of the next panel column come first.
+int dcx_submit_potrf_tiles(dc_runtime *rt, const std::vector<dc_handle> &A, int64_t T) {
+  auto at = [&](int64_t i, int64_t j) { return A[i * T + j]; };
+  for (int64_t k = 0; k < T; ++k) {
+    TRY(submit1(rt, DC_POTRF, at(k, k), DC_RW, 0));
+    for (int64_t i = k + 1; i < T; ++i)
+      TRY(submit2(rt, DC_TRSM, at(k, k), DC_R, at(i, k), DC_RW, i == k + 1 ? 0 : 1));
+    for (int64_t i = k + 1; i < T; ++i) {
+      TRY(submit2(rt, DC_SYRK, at(i, k), DC_R, at(i, i), DC_RW, i == k + 1 ? 0 : 2));
+      for (int64_t j = k + 1; j < i; ++j)
+        TRY(submit3(rt, DC_GEMM, at(i, k), DC_R, at(j, k), DC_R, at(i, j), DC_RW,
+                    j == k + 1 ? 1 : 2));
+    }
+  }
+  return 0;
+}
+
+// Forward then backward sweep on partitioned L tiles and RHS row blocks.
+int dcx_submit_potrs_tiles(dc_runtime *rt, const std::vector<dc_handle> &L, int64_t T,
+                           const std::vector<dc_handle> &B) {
+  auto at = [&](int64_t i, int64_t j) { return L[i * T + j]; };
+  for (int64_t k = 0; k < T; ++k) {
+    TRY(submit2(rt, DC_TRSM_L, at(k, k), DC_R, B[k], DC_RW, 0));
+    for (int64_t i = k + 1; i < T; ++i)
+      TRY(submit3(rt, DC_GEMM_RHS_N, at(i, k), DC_R, B[k], DC_R, B[i], DC_RW, i == k + 1 ? 0 : 1));
+  }
+  for (int64_t k = T - 1; k >= 0; --k) {
+    TRY(submit2(rt, DC_TRSM_LT, at(k, k), DC_R, B[k], DC_RW, 0));
+    for (int64_t i = k - 1; i >= 0; --i)
+      TRY(submit3(rt, DC_GEMM_RHS_T, at(k, i), DC_R, B[k], DC_R, B[i], DC_RW, i == k - 1 ? 0 : 1));
+  }
+  return 0;
+}
+
+extern "C" int dc_potrf(dc_runtime *rt, dc_handle A, int64_t tile) {
+  if (!rt) return -EINVAL;
+  Handle *p = rt->get(A);
+  if (!p) return -ENOENT;
+  if (p->rows != p->cols || p->dtype != DC_F64 || tile < 1 || tile > dcx::MAX_TILE)
+    return -EINVAL;
+  if (p->partitioned) return -EBUSY;
+  if (p->rows == 0) { p->info = 0; return 0; }
+  Tiles t;
+  TRY(t.open(rt, A, tile));
+  TRY(dcx_submit_potrf_tiles(rt, t.ids, t.tr));
+  return dc_wait_all(rt);
+}
+
+extern "C" int dc_potrs(dc_runtime *rt, dc_handle L, dc_handle B, int64_t tile) {
+  if (!rt) return -EINVAL;
+  Handle *pl = rt->get(L);
+  Handle *pb = rt->get(B);
+  if (!pl || !pb) return -ENOENT;
+  if (pl->rows != pl->cols || pb->rows != pl->rows || pb->dtype != DC_F64 ||
+      pl->dtype != DC_F64 || tile < 1 || tile > dcx::MAX_TILE)
+    return -EINVAL;
+  if (pl->partitioned || pb->partitioned) return -EBUSY;
+  if (pl->rows == 0 || pb->cols == 0) return 0;
+  Tiles tl, tb;
+  TRY(tl.open(rt, L, tile));
+  TRY(tb.open(rt, B, tile));
+  // each column block of B is an independent right-hand-side group
+  std::vector<dc_handle> rows(tl.tr);
+  for (int64_t j = 0; j < tb.tc; ++j) {
+    for (int64_t i = 0; i < tl.tr; ++i) rows[i] = tb.at(i, j);
+    TRY(dcx_submit_potrs_tiles(rt, tl.ids, tl.tr, rows));
+  }
+  return dc_wait_all(rt);
+}
+
+extern "C" int dc_posv_ir(dc_runtime *rt, dc_handle A, dc_handle B, dc_handle X, int64_t tile,
+                          dc_dtype upd, double tol, int maxit, dc_ir_report *rep) {
+  (void)rt; (void)A; (void)B; (void)X; (void)tile; (void)upd; (void)tol; (void)maxit; (void)rep;
+  return -ENOSYS;
+}

@@ -1,0 +1,856 @@
+// Host runtime of dagchol: handles, partitioning, access-mode dependency
+// inference, graph upload and executor launch.  Implements include/dagchol.h.
+//
+// Tasks submitted between two flushes form one graph.  At flush the graph is
+// laid out in one contiguous block (descriptors, dependency counters, CSR
+// successor lists, queue slots pre-filled with the initially ready work
+// units), copied to the device in one transfer, and run by one persistent
+// executor launch on the runtime's stream.
+#include <hip/hip_runtime.h>
+
+#include <errno.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <map>
+#include <new>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/dagchol.h"
+#include "exec_abi.h"
+#include "runtime_internal.h"
+
+using namespace dcx;
+
+// ------------------------------------------------------------------ helpers
+
+static thread_local std::string g_last_error;
+
+static int fail_hip(hipError_t e, const char *what) {
+  g_last_error = std::string(what) + ": " + hipGetErrorName(e) + " (" + hipGetErrorString(e) + ")";
+  return -EIO;
+}
+
+extern "C" const char *dc_last_error(void) { return g_last_error.c_str(); }
+
+static size_t dtype_size(int t) { return t == DC_F64 ? 8 : t == DC_F32 ? 4 : 2; }
+
+static int64_t align_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
+
+Handle *dc_runtime::get(dc_handle h) {
+  if (h <= 0 || h > (dc_handle)handles.size()) return nullptr;
+  Handle *p = &handles[h - 1];
+  return p->alive ? p : nullptr;
+}
+
+dc_handle dc_runtime::root_of(dc_handle h) {
+  while (true) {
+    Handle *p = &handles[h - 1];
+    if (!p->parent) return h;
+    h = p->parent;
+  }
+}
+
+void dc_runtime::reset_graph_state() {
+  for (dc_handle h : touched) {
+    Handle *p = &handles[h - 1];
+    p->last_writer = -1;
+    p->readers.clear();
+    p->pending = 0;
+  }
+  touched.clear();
+  tasks.clear();
+}
+
+// ---------------------------------------------------------------- lifecycle
+
+extern "C" void dc_config_default(dc_config *cfg) {
+  if (!cfg) return;
+  memset(cfg, 0, sizeof(*cfg));
+  cfg->device = 0;
+  cfg->watchdog_ms = 60000;
+}
+
+extern "C" int dc_init(dc_runtime **out, const dc_config *cfg) {
+  if (!out) return -EINVAL;
+  *out = nullptr;
+  dc_config c;
+  if (cfg) c = *cfg; else dc_config_default(&c);
+  if (c.watchdog_ms <= 0) c.watchdog_ms = 60000;
+  dc_runtime *rt = new (std::nothrow) dc_runtime();
+  if (!rt) return -ENOMEM;
+  rt->cfg = c;
+  if (c.device >= 0) {
+    int ndev = 0;
+    hipError_t he = hipGetDeviceCount(&ndev);
+    if (he != hipSuccess) { delete rt; return fail_hip(he, "hipGetDeviceCount"); }
+    if (c.device >= ndev) {
+      delete rt;
+      g_last_error = "device ordinal out of range";
+      return -EIO;
+    }
+    he = hipSetDevice(c.device);
+    if (he != hipSuccess) { delete rt; return fail_hip(he, "hipSetDevice"); }
+    if (c.stream) {
+      rt->stream = (hipStream_t)c.stream;
+    } else {
+      he = hipStreamCreateWithFlags(&rt->stream, hipStreamNonBlocking);
+      if (he != hipSuccess) { delete rt; return fail_hip(he, "hipStreamCreate"); }
+      rt->own_stream = true;
+    }
+    int cus = 0;
+    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c.device);
+    he = (hipError_t)dcx_level_setup();
+    if (he != hipSuccess) { delete rt; return fail_hip(he, "hipFuncSetAttribute"); }
+    rt->num_cus = std::max(1, cus);
+    rt->default_workers = rt->num_cus;
+    int rate_khz = 0;
+    hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, c.device);
+    rt->wall_clock_khz = rate_khz > 0 ? rate_khz : 100000;
+  }
+  *out = rt;
+  return 0;
+}
+
+static void free_device(dc_runtime *rt) {
+  if (rt->arena_dev) hipFree(rt->arena_dev);
+  if (rt->arena_host) hipHostFree(rt->arena_host);
+  rt->arena_dev = nullptr;
+  rt->arena_host = nullptr;
+  rt->arena_cap = 0;
+}
+
+extern "C" int dc_shutdown(dc_runtime *rt) {
+  if (!rt) return -EINVAL;
+  int err = 0;
+  if (rt->cfg.device >= 0) {
+    err = dc_wait_all(rt);
+    free_device(rt);
+    if (rt->own_stream) hipStreamDestroy(rt->stream);
+  }
+  delete rt;
+  return err;
+}
+
+// ------------------------------------------------------------ registration
+
+static int register_common(dc_runtime *rt, dc_handle *out, void *ptr, int64_t rows,
+                           int64_t cols, int64_t ld, dc_dtype dtype, int kind) {
+  if (!rt || !out || !ptr || rows < 0 || cols < 0 || ld < cols || ld < 1) return -EINVAL;
+  if (dtype != DC_F64 && dtype != DC_F32 && dtype != DC_BF16) return -EINVAL;
+  if (rt->by_ptr.count(ptr)) return -EBUSY;
+  Handle h;
+  h.kind = kind;
+  h.ptr = ptr;
+  h.rows = rows;
+  h.cols = cols;
+  h.ld = ld;
+  h.dtype = dtype;
+  h.alive = true;
+  rt->handles.push_back(h);
+  dc_handle id = (dc_handle)rt->handles.size();
+  rt->by_ptr[ptr] = id;
+  *out = id;
+  return 0;
+}
+
+extern "C" int dc_vector_register(dc_runtime *rt, dc_handle *out, void *ptr, int64_t nx,
+                                  dc_dtype dtype) {
+  return register_common(rt, out, ptr, nx, 1, 1, dtype, HK_VECTOR);
+}
+
+extern "C" int dc_matrix_register(dc_runtime *rt, dc_handle *out, void *ptr, int64_t rows,
+                                  int64_t cols, int64_t ld, dc_dtype dtype) {
+  return register_common(rt, out, ptr, rows, cols, ld, dtype, HK_MATRIX);
+}
+
+extern "C" int dc_handle_lookup(dc_runtime *rt, const void *ptr, dc_handle *out) {
+  if (!rt || !out) return -EINVAL;
+  *out = 0;
+  auto it = rt->by_ptr.find((void *)ptr);
+  if (it == rt->by_ptr.end()) return -ENOENT;
+  *out = it->second;
+  return 0;
+}
+
+static bool has_pending(dc_runtime *rt, dc_handle h) {
+  Handle *p = rt->get(h);
+  if (!p) return false;
+  if (p->pending) return true;
+  for (dc_handle t : p->tiles)
+    if (has_pending(rt, t)) return true;
+  return false;
+}
+
+extern "C" int dc_matrix_partition(dc_runtime *rt, dc_handle m, int64_t tile,
+                                   dc_handle *tiles_out) {
+  if (!rt) return -EINVAL;
+  Handle *p = rt->get(m);
+  if (!p) return -ENOENT;
+  if (p->kind != HK_MATRIX || tile < 1 || !tiles_out) return -EINVAL;
+  if (p->partitioned) return -EBUSY;
+  if (p->pending) return -EBUSY;
+  const int64_t tr = (p->rows + tile - 1) / tile, tc = (p->cols + tile - 1) / tile;
+  std::vector<dc_handle> ids;
+  ids.reserve(tr * tc);
+  const size_t es = dtype_size(p->dtype);
+  // copy the fields we need: push_back may move the handle storage
+  const Handle parent = *p;
+  for (int64_t I = 0; I < tr; ++I)
+    for (int64_t J = 0; J < tc; ++J) {
+      Handle h;
+      h.kind = HK_MATRIX;
+      h.ptr = (char *)parent.ptr + (size_t)((I * tile) * parent.ld + J * tile) * es;
+      h.rows = std::min(tile, parent.rows - I * tile);
+      h.cols = std::min(tile, parent.cols - J * tile);
+      h.ld = parent.ld;
+      h.dtype = parent.dtype;
+      h.parent = m;
+      h.ti = I;
+      h.tj = J;
+      h.row_off = parent.row_off + I * tile;
+      h.alive = true;
+      rt->handles.push_back(h);
+      ids.push_back((dc_handle)rt->handles.size());
+    }
+  p = rt->get(m);
+  p->partitioned = true;
+  p->tile = tile;
+  p->trows = tr;
+  p->tcols = tc;
+  p->tiles = ids;
+  std::copy(ids.begin(), ids.end(), tiles_out);
+  return 0;
+}
+
+static void drop_tiles(dc_runtime *rt, dc_handle m) {
+  Handle *p = rt->get(m);
+  if (!p) return;
+  for (dc_handle t : p->tiles) {
+    drop_tiles(rt, t);
+    Handle *c = rt->get(t);
+    if (c) c->alive = false;
+  }
+  p->tiles.clear();
+  p->partitioned = false;
+}
+
+extern "C" int dc_matrix_unpartition(dc_runtime *rt, dc_handle m) {
+  if (!rt) return -EINVAL;
+  Handle *p = rt->get(m);
+  if (!p) return -ENOENT;
+  if (!p->partitioned) return -EINVAL;
+  if (has_pending(rt, m)) {
+    int e = dc_wait_all(rt);
+    if (e) return e;
+  }
+  drop_tiles(rt, m);
+  return 0;
+}
+
+extern "C" int dc_matrix_tiles(dc_runtime *rt, dc_handle m, int64_t *trows, int64_t *tcols) {
+  if (!rt || !trows || !tcols) return -EINVAL;
+  Handle *p = rt->get(m);
+  if (!p) return -ENOENT;
+  if (!p->partitioned) return -EINVAL;
+  *trows = p->trows;
+  *tcols = p->tcols;
+  return 0;
+}
+
+extern "C" int dc_unregister(dc_runtime *rt, dc_handle h) {
+  if (!rt) return -EINVAL;
+  Handle *p = rt->get(h);
+  if (!p) return -ENOENT;
+  if (p->parent) return -EINVAL;   // tiles go away with unpartition
+  if (has_pending(rt, h)) {
+    int e = dc_wait_all(rt);
+    if (e) return e;
+  }
+  drop_tiles(rt, h);
+  p = rt->get(h);
+  rt->by_ptr.erase(p->ptr);
+  p->alive = false;
+  return 0;
+}
+
+extern "C" int dc_acquire(dc_runtime *rt, dc_handle h, dc_mode mode) {
+  if (!rt) return -EINVAL;
+  if (!rt->get(h)) return -ENOENT;
+  if (mode != DC_R && mode != DC_W && mode != DC_RW) return -EINVAL;
+  if (has_pending(rt, h)) return dc_wait_all(rt);
+  return 0;
+}
+
+extern "C" int dc_release(dc_runtime *rt, dc_handle h) {
+  if (!rt) return -EINVAL;
+  return rt->get(h) ? 0 : -ENOENT;
+}
+
+extern "C" int dc_get_info(dc_runtime *rt, dc_handle m, int64_t *info) {
+  if (!rt || !info) return -EINVAL;
+  Handle *p = rt->get(m);
+  if (!p) return -ENOENT;
+  *info = rt->handles[rt->root_of(m) - 1].info;
+  return 0;
+}
+
+// --------------------------------------------------------------- submission
+
+struct KindSig {
+  int nbuf;
+  int modes[4];
+};
+
+static const KindSig kSig[DC_NUM_KINDS] = {
+    {1, {DC_RW}},                       // POTRF
+    {2, {DC_R, DC_RW}},                 // TRSM
+    {2, {DC_R, DC_RW}},                 // SYRK
+    {3, {DC_R, DC_R, DC_RW}},           // GEMM
+    {2, {DC_R, DC_RW}},                 // TRSM_L
+    {3, {DC_R, DC_R, DC_RW}},           // GEMM_RHS_N
+    {2, {DC_R, DC_RW}},                 // TRSM_LT
+    {3, {DC_R, DC_R, DC_RW}},           // GEMM_RHS_T
+    {1, {DC_RW}},                       // SCAL
+    {2, {DC_R, DC_W}},                  // CAST
+    {4, {DC_R, DC_R, DC_R, DC_W}},      // RESID
+    {2, {DC_R, DC_RW}},                 // AXPY
+};
+
+static int units_for(const TaskDesc &d) {
+  auto cdiv = [](int64_t a, int64_t b) { return (int)((a + b - 1) / b); };
+  switch (d.kind) {
+    case K_GEMM: return std::max(1, cdiv(d.m, GEMM_UNIT) * cdiv(d.n, GEMM_UNIT));
+    case K_SYRK: { int p = cdiv(d.m, GEMM_UNIT); return std::max(1, p * (p + 1) / 2); }
+    case K_TRSM: return std::max(1, cdiv(d.m, trsm_rows(d.n)));
+    case K_GEMM_RHS_N: case K_GEMM_RHS_T: case K_CAST: case K_RESID: case K_AXPY:
+      return std::max(1, cdiv(d.m, ROW_UNIT));
+    case K_SCAL: return std::max(1, cdiv(d.m, 4096));
+    default: return 1;
+  }
+}
+
+// Builds the descriptor of a task from its handles; checks shapes and dtypes.
+static int make_desc(dc_runtime *rt, dc_kind kind, const std::vector<Handle *> &H,
+                     const void *cl, size_t cls, TaskDesc &d) {
+  memset(&d, 0, sizeof(d));
+  d.kind = kind;
+  d.matrix = -1;
+  auto mat = [](Handle *h) { return h->kind == HK_MATRIX || h->kind == HK_VECTOR; };
+  for (Handle *h : H)
+    if (!mat(h)) return -EINVAL;
+  auto f64 = [](Handle *h) { return h->dtype == DC_F64; };
+  switch (kind) {
+    case DC_POTRF: {
+      Handle *D = H[0];
+      if (!f64(D) || D->rows != D->cols || D->rows > MAX_TILE) return -EINVAL;
+      d.m = (int)D->rows;
+      d.c = D->ptr; d.ldc = D->ld; d.tc = D->dtype;
+      int64_t row0 = D->row_off;
+      if (cl && cls >= sizeof(int64_t)) memcpy(&row0, cl, sizeof(int64_t));
+      d.row0 = row0;
+      break;
+    }
+    case DC_TRSM: {
+      Handle *L = H[0], *X = H[1];
+      if (!f64(L) || !f64(X)) return -EINVAL;
+      if (L->rows != L->cols || X->cols != L->rows || L->rows > MAX_TILE) return -EINVAL;
+      d.m = (int)X->rows; d.n = (int)L->rows;
+      d.a = L->ptr; d.lda = L->ld; d.ta = L->dtype;
+      d.c = X->ptr; d.ldc = X->ld; d.tc = X->dtype;
+      break;
+    }
+    case DC_SYRK: {
+      Handle *X = H[0], *C = H[1];
+      if (!f64(X) || !f64(C)) return -EINVAL;
+      if (C->rows != C->cols || X->rows != C->rows) return -EINVAL;
+      d.m = (int)C->rows; d.k = (int)X->cols;
+      d.a = X->ptr; d.lda = X->ld; d.ta = X->dtype;
+      d.c = C->ptr; d.ldc = C->ld; d.tc = C->dtype;
+      break;
+    }
+    case DC_GEMM: {
+      Handle *X = H[0], *Y = H[1], *C = H[2];
+      if (!f64(X) || !f64(Y) || !f64(C)) return -EINVAL;
+      if (X->rows != C->rows || Y->rows != C->cols || X->cols != Y->cols) return -EINVAL;
+      d.m = (int)C->rows; d.n = (int)C->cols; d.k = (int)X->cols;
+      d.a = X->ptr; d.lda = X->ld; d.ta = X->dtype;
+      d.b = Y->ptr; d.ldb = Y->ld; d.tb = Y->dtype;
+      d.c = C->ptr; d.ldc = C->ld; d.tc = C->dtype;
+      break;
+    }
+    case DC_TRSM_L: case DC_TRSM_LT: {
+      Handle *L = H[0], *B = H[1];
+      if (!f64(B) || L->dtype == DC_BF16) return -EINVAL;
+      if (L->rows != L->cols || B->rows != L->rows) return -EINVAL;
+      d.m = (int)L->rows; d.n = (int)B->cols;
+      d.a = L->ptr; d.lda = L->ld; d.ta = L->dtype;
+      d.c = B->ptr; d.ldc = B->ld; d.tc = B->dtype;
+      break;
+    }
+    case DC_GEMM_RHS_N: case DC_GEMM_RHS_T: {
+      Handle *L = H[0], *Y = H[1], *B = H[2];
+      if (!f64(Y) || !f64(B) || L->dtype == DC_BF16) return -EINVAL;
+      const bool t = kind == DC_GEMM_RHS_T;
+      const int64_t lrows = t ? L->cols : L->rows, lk = t ? L->rows : L->cols;
+      if (lrows != B->rows || lk != Y->rows || Y->cols != B->cols) return -EINVAL;
+      d.m = (int)B->rows; d.n = (int)B->cols; d.k = (int)lk;
+      d.a = L->ptr; d.lda = L->ld; d.ta = L->dtype;
+      d.b = Y->ptr; d.ldb = Y->ld; d.tb = Y->dtype;
+      d.c = B->ptr; d.ldc = B->ld; d.tc = B->dtype;
+      break;
+    }
+    case DC_SCAL: {
+      Handle *X = H[0];
+      if (X->dtype != DC_F32 || X->cols != 1) return -EINVAL;
+      float f = 1.0f;
+      if (!cl || cls != sizeof(float)) return -EINVAL;
+      memcpy(&f, cl, sizeof(float));
+      d.m = (int)X->rows; d.alpha = f;
+      d.c = X->ptr; d.ldc = X->ld; d.tc = X->dtype;
+      break;
+    }
+    case DC_CAST: {
+      Handle *S = H[0], *D = H[1];
+      if (S->rows != D->rows || S->cols != D->cols) return -EINVAL;
+      d.m = (int)S->rows; d.n = (int)S->cols;
+      d.a = S->ptr; d.lda = S->ld; d.ta = S->dtype;
+      d.c = D->ptr; d.ldc = D->ld; d.tc = D->dtype;
+      break;
+    }
+    case DC_RESID: {
+      Handle *A = H[0], *X = H[1], *B = H[2], *R = H[3];
+      if (!f64(A) || !f64(X) || !f64(B) || !f64(R)) return -EINVAL;
+      if (A->rows != A->cols || X->rows != A->rows || B->rows != A->rows || R->rows != A->rows ||
+          X->cols != B->cols || R->cols != B->cols)
+        return -EINVAL;
+      d.m = (int)A->rows; d.n = (int)B->cols;
+      d.a = A->ptr; d.lda = A->ld; d.ta = A->dtype;
+      d.b = X->ptr; d.ldb = X->ld; d.tb = X->dtype;
+      d.d = B->ptr; d.ldd = B->ld;
+      d.c = R->ptr; d.ldc = R->ld; d.tc = R->dtype;
+      break;
+    }
+    case DC_AXPY: {
+      Handle *D = H[0], *X = H[1];
+      if (!f64(D) || !f64(X) || D->rows != X->rows || D->cols != X->cols) return -EINVAL;
+      d.m = (int)X->rows; d.n = (int)X->cols;
+      d.a = D->ptr; d.lda = D->ld; d.ta = D->dtype;
+      d.c = X->ptr; d.ldc = X->ld; d.tc = X->dtype;
+      break;
+    }
+    default:
+      return -EINVAL;
+  }
+  (void)rt;
+  return 0;
+}
+
+extern "C" int dc_task_submit(dc_runtime *rt, dc_kind kind, int nbuf, const dc_handle *bufs,
+                              const dc_mode *modes, const void *cl_args, size_t cl_args_size,
+                              int priority) {
+  if (!rt) return -EINVAL;
+  if ((int)kind < 0 || kind >= DC_NUM_KINDS) return -EINVAL;
+  const KindSig &sig = kSig[kind];
+  if (nbuf != sig.nbuf || (nbuf > 0 && (!bufs || !modes))) return -EINVAL;
+  if (cl_args_size > 64 || (cl_args_size && !cl_args)) return -EINVAL;
+  std::vector<Handle *> H(nbuf);
+  for (int i = 0; i < nbuf; ++i) {
+    Handle *p = rt->get(bufs[i]);
+    if (!p) return -ENOENT;
+    if (p->partitioned) return -EBUSY;
+    const int want = sig.modes[i], got = modes[i];
+    if (got != DC_R && got != DC_W && got != DC_RW) return -EINVAL;
+    // a write-only declaration may be given as read-write; nothing else differs
+    const bool ok = (got == want) || (want == DC_W && got == DC_RW) || (want == DC_RW && got == DC_W);
+    if (!ok) return -EINVAL;
+    H[i] = p;
+  }
+  TaskDesc d;
+  int e = make_desc(rt, kind, H, cl_args, cl_args_size, d);
+  if (e) return e;
+  d.nunits = units_for(d);
+  if (rt->tasks.size() >= (size_t)INT32_MAX / 2) return -ENOMEM;
+
+  // numerical-status slot: the root matrix of the factor this task touches
+  if (kind <= DC_GEMM_RHS_T) {
+    dc_handle root = rt->root_of(bufs[0]);
+    if (kind == DC_POTRF) root = rt->root_of(bufs[0]);
+    auto it = rt->slot_of.find(root);
+    int slot;
+    if (it == rt->slot_of.end()) {
+      slot = (int)rt->slot_roots.size();
+      rt->slot_of[root] = slot;
+      rt->slot_roots.push_back(root);
+      rt->slot_factor.push_back(0);
+    } else {
+      slot = it->second;
+    }
+    d.matrix = slot;
+    if (kind == DC_POTRF) rt->slot_factor[slot] = 1;
+  }
+
+  const int64_t t = (int64_t)rt->tasks.size();
+  Task task;
+  task.desc = d;
+  task.prio = std::min(std::max(priority, 0), MAX_LANES - 1);
+  std::vector<int64_t> raw, war;
+  for (int i = 0; i < nbuf; ++i) {
+    Handle *p = rt->get(bufs[i]);
+    if (!p->pending) rt->touched.push_back(bufs[i]);
+    p->pending = 1;
+    if (modes[i] & DC_W) {
+      if (p->last_writer >= 0) raw.push_back(p->last_writer);
+      for (int64_t r : p->readers)
+        if (r != t) war.push_back(r);
+    } else if (p->last_writer >= 0) {
+      raw.push_back(p->last_writer);
+    }
+  }
+  for (int i = 0; i < nbuf; ++i) {
+    Handle *p = rt->get(bufs[i]);
+    if (modes[i] & DC_W) {
+      p->last_writer = t;
+      p->readers.clear();
+    } else {
+      p->readers.push_back(t);
+    }
+  }
+  std::sort(raw.begin(), raw.end());
+  raw.erase(std::unique(raw.begin(), raw.end()), raw.end());
+  std::sort(war.begin(), war.end());
+  war.erase(std::unique(war.begin(), war.end()), war.end());
+  std::vector<int64_t> only_war;
+  std::set_difference(war.begin(), war.end(), raw.begin(), raw.end(), std::back_inserter(only_war));
+  task.preds = raw;
+  task.preds.insert(task.preds.end(), only_war.begin(), only_war.end());
+  std::sort(task.preds.begin(), task.preds.end());
+  task.nwar = (int64_t)only_war.size();
+  rt->tasks.push_back(std::move(task));
+  return 0;
+}
+
+// ------------------------------------------------------------ graph queries
+
+extern "C" int dc_graph_stats_get(dc_runtime *rt, dc_graph_stats *out) {
+  if (!rt || !out) return -EINVAL;
+  memset(out, 0, sizeof(*out));
+  out->ntasks = (int64_t)rt->tasks.size();
+  std::vector<int64_t> depth(rt->tasks.size(), 0);
+  for (size_t t = 0; t < rt->tasks.size(); ++t) {
+    const Task &k = rt->tasks[t];
+    out->nedges += (int64_t)k.preds.size();
+    out->nwar_edges += k.nwar;
+    out->nunits += k.desc.nunits;
+    int64_t dmax = 0;
+    for (int64_t p : k.preds) dmax = std::max(dmax, depth[p]);
+    depth[t] = dmax + 1;
+    out->critical_path = std::max(out->critical_path, depth[t]);
+  }
+  return 0;
+}
+
+extern "C" int dc_graph_preds(dc_runtime *rt, int64_t t, int64_t *preds, int64_t cap,
+                              int64_t *count) {
+  if (!rt || !count || cap < 0 || (cap > 0 && !preds)) return -EINVAL;
+  if (t < 0 || t >= (int64_t)rt->tasks.size()) return -ENOENT;
+  const auto &p = rt->tasks[t].preds;
+  *count = (int64_t)p.size();
+  for (int64_t i = 0; i < std::min<int64_t>(cap, (int64_t)p.size()); ++i) preds[i] = p[i];
+  return 0;
+}
+
+extern "C" int dc_trace_get(dc_runtime *rt, int64_t t, int64_t *start_ns, int64_t *end_ns,
+                            int32_t *worker, int32_t *kind) {
+  if (!rt || !start_ns || !end_ns || !worker || !kind) return -EINVAL;
+  if (rt->trace_host.empty() || t < 0 || t >= (int64_t)rt->trace_kind.size()) return -ENOENT;
+  const double ns_per_tick = 1e6 / (double)rt->wall_clock_khz;
+  *start_ns = (int64_t)((double)(rt->trace_host[3 * t] - rt->trace_t0) * ns_per_tick);
+  *end_ns = (int64_t)((double)(rt->trace_host[3 * t + 1] - rt->trace_t0) * ns_per_tick);
+  *worker = (int32_t)rt->trace_host[3 * t + 2];
+  *kind = rt->trace_kind[t];
+  return 0;
+}
+
+// ---------------------------------------------------------------- execution
+
+static int hip_err(hipError_t e) { return e == hipSuccess ? 0 : -EIO; }
+
+// Waits for the launched graph and copies back its status and info words.
+static int finalize(dc_runtime *rt) {
+  if (!rt->inflight) return 0;
+  rt->inflight = false;
+  hipError_t e = hipStreamSynchronize(rt->stream);
+  if (e != hipSuccess) return fail_hip(e, "hipStreamSynchronize");
+  Inflight &f = rt->fl;
+  // status, info and failed words live at the end of the arena
+  std::vector<char> tail(f.tail_bytes);
+  e = hipMemcpy(tail.data(), (char *)rt->arena_dev + f.tail_off, f.tail_bytes,
+                hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return -EIO;
+  int32_t status = 0;
+  for (size_t s = 0; s < f.slot_roots.size(); ++s) {
+    if (!f.slot_factor[s]) continue;   // only a factorisation sets the status
+    int64_t info;
+    memcpy(&info, tail.data() + (f.info_off - f.tail_off) + s * 8, 8);
+    Handle &h = rt->handles[f.slot_roots[s] - 1];
+    h.info = info;
+  }
+  if (f.trace_off) {
+    rt->trace_host.resize(3 * (size_t)f.ntasks);
+    e = hipMemcpy(rt->trace_host.data(), (char *)rt->arena_dev + f.trace_off,
+                  rt->trace_host.size() * 8, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return -EIO;
+    rt->trace_t0 = INT64_MAX;
+    for (int64_t t = 0; t < f.ntasks; ++t) rt->trace_t0 = std::min(rt->trace_t0, rt->trace_host[3 * t]);
+    rt->trace_kind = f.kinds;
+  }
+  return status;
+}
+
+// LDS bytes the level kernel needs for a unit of this task.
+static size_t lds_for(const TaskDesc &d) {
+  switch (d.kind) {
+    case K_GEMM: case K_SYRK: return (size_t)2 * 2 * GEMM_UNIT * 17 * 8;
+    case K_TRSM: return (size_t)(trsm_rows(d.n) * (d.n + 1) + PANEL * (PANEL + 1)) * 8;
+    case K_POTRF: return (size_t)(PANEL * (PANEL + 1) + 8) * 8;
+    case K_TRSM_L: case K_TRSM_LT: return (size_t)(16 * 16 * 16 + 16 * 16) * 8;
+    case K_GEMM_RHS_T: return (size_t)(4 * 64 * 8) * 8;
+    case K_RESID: return (size_t)(2 * 64 * 8 + 4 * 64 * 8) * 8;
+    default: return 16;
+  }
+}
+
+// Rough duration (ns) of a task on one CU, for balancing levels.
+static double cost_ns(const TaskDesc &d) {
+  const double m = d.m, n = d.n, k = d.k;
+  switch (d.kind) {
+    case K_GEMM: return 2.0 * m * n * k / 250.0;
+    case K_SYRK: return m * m * k / 250.0;
+    case K_TRSM: return m * n * n / 120.0;
+    case K_POTRF: return m * m * m / 3.0 / 40.0 + 2000.0;
+    case K_TRSM_L: case K_TRSM_LT: return m * m * 8.0 / 20.0 + 2000.0;
+    case K_GEMM_RHS_N: case K_GEMM_RHS_T: return m * k * 8.0 / 50.0;
+    case K_RESID: return m * m * 8.0 / 50.0;
+    default: return 1000.0 + m * (n > 0 ? n : 1) * 8.0 / 50.0;
+  }
+}
+
+// Splits the pending graph into levels.  asap = earliest level (longest
+// chain of predecessors), alap = latest level that still keeps the number of
+// levels at the critical path length; each task goes, in submission order
+// (a topological order), to the level in [max(level of preds) + 1, alap]
+// where it lengthens the estimated level time least.  These are the
+// compiler-style downward/upward ranks of the paper's Section 5.3 used as a
+// static schedule.
+static int64_t assign_levels(dc_runtime *rt, int workers, std::vector<int32_t> &level) {
+  const int64_t nt = (int64_t)rt->tasks.size();
+  std::vector<int32_t> asap(nt, 0), alap(nt, 0);
+  int32_t depth = 0;
+  for (int64_t t = 0; t < nt; ++t) {
+    int32_t a = 0;
+    for (int64_t p : rt->tasks[t].preds) a = std::max(a, asap[p] + 1);
+    asap[t] = a;
+    depth = std::max(depth, a);
+  }
+  for (int64_t t = 0; t < nt; ++t) alap[t] = depth;
+  for (int64_t t = nt - 1; t >= 0; --t)
+    for (int64_t p : rt->tasks[t].preds) alap[p] = std::min(alap[p], alap[t] - 1);
+  const int64_t nl = (int64_t)depth + 1;
+  std::vector<double> lsum(nl, 0.0), lmax(nl, 0.0);
+  level.assign(nt, 0);
+  const double w = std::max(1, workers);
+  const int window = 48;
+  for (int64_t t = 0; t < nt; ++t) {
+    const Task &k = rt->tasks[t];
+    int32_t lo = 0;
+    for (int64_t p : k.preds) lo = std::max(lo, level[p] + 1);
+    const int32_t hi = std::max(lo, std::min(alap[t], lo + window));
+    const double c = cost_ns(k.desc);
+    const double cu = c / std::max(1, k.desc.nunits);
+    int32_t best = lo;
+    double best_inc = 1e300;
+    for (int32_t L = lo; L <= hi; ++L) {
+      const double old_t = std::max(lmax[L], lsum[L] / w);
+      const double new_t = std::max(std::max(lmax[L], cu), (lsum[L] + c) / w);
+      const double inc = new_t - old_t;
+      if (inc < best_inc * 0.999) { best_inc = inc; best = L; }
+      if (inc <= 0.0) break;
+    }
+    level[t] = best;
+    lsum[best] += c;
+    lmax[best] = std::max(lmax[best], cu);
+  }
+  return nl;
+}
+
+extern "C" int dc_flush(dc_runtime *rt) {
+  if (!rt) return -EINVAL;
+  if (rt->tasks.empty()) return 0;
+  auto drop = [&]() {
+    rt->reset_graph_state();
+    rt->slot_of.clear();
+    rt->slot_roots.clear();
+    rt->slot_factor.clear();
+  };
+  if (rt->cfg.device < 0) { drop(); return -ENODEV; }
+  int err = finalize(rt);
+  if (err) { drop(); return err; }
+  auto t_build0 = std::chrono::steady_clock::now();
+  const int64_t nt = (int64_t)rt->tasks.size();
+  const int workers_cfg = rt->cfg.workers > 0 ? rt->cfg.workers : rt->num_cus;
+  std::vector<int32_t> level;
+  const int64_t nl = assign_levels(rt, workers_cfg, level);
+  int64_t total_units = 0;
+  std::vector<int64_t> lcount(nl, 0);
+  for (int64_t t = 0; t < nt; ++t) {
+    total_units += rt->tasks[t].desc.nunits;
+    lcount[level[t]] += rt->tasks[t].desc.nunits;
+  }
+  if (total_units >= INT32_MAX) { drop(); return -ENOMEM; }
+  const int nslots_roots = (int)rt->slot_roots.size();
+  const bool trace = rt->cfg.trace != 0;
+
+  int64_t off = 0;
+  auto take = [&](int64_t bytes) { int64_t o = off; off = align_up(off + bytes, 256); return o; };
+  const int64_t o_desc = take(nt * (int64_t)sizeof(TaskDesc));
+  const int64_t o_items = take(total_units * 8);
+  const int64_t o_cnt = take(nl * 8);
+  const int64_t o_tail = off;
+  const int64_t o_info = take(std::max(nslots_roots, 1) * 8);
+  const int64_t o_failed = take(std::max(nslots_roots, 1) * 4);
+  const int64_t tail_end = off;
+  const int64_t o_trace = trace ? take(nt * 3 * 8) : 0;
+  const int64_t total = off;
+
+  if (total > rt->arena_cap) {
+    free_device(rt);
+    int64_t cap = align_up(total + total / 4, 1 << 20);
+    if (hipMalloc(&rt->arena_dev, cap) != hipSuccess) { rt->arena_dev = nullptr; drop(); return -ENOMEM; }
+    if (hipHostMalloc(&rt->arena_host, cap, hipHostMallocDefault) != hipSuccess) {
+      hipFree(rt->arena_dev);
+      rt->arena_dev = nullptr;
+      rt->arena_host = nullptr;
+      drop();
+      return -ENOMEM;
+    }
+    rt->arena_cap = cap;
+  }
+  char *hb = (char *)rt->arena_host;
+  TaskDesc *desc = (TaskDesc *)(hb + o_desc);
+  uint64_t *items = (uint64_t *)(hb + o_items);
+  std::vector<int64_t> lbegin(nl, 0);
+  for (int64_t L = 1; L < nl; ++L) lbegin[L] = lbegin[L - 1] + lcount[L - 1];
+  // order inside a level: urgent priority lanes first, then longer units
+  std::vector<int64_t> order(nt);
+  for (int64_t t = 0; t < nt; ++t) order[t] = t;
+  std::stable_sort(order.begin(), order.end(), [&](int64_t x, int64_t y) {
+    if (level[x] != level[y]) return level[x] < level[y];
+    if (rt->tasks[x].prio != rt->tasks[y].prio) return rt->tasks[x].prio < rt->tasks[y].prio;
+    const double cx = cost_ns(rt->tasks[x].desc) / rt->tasks[x].desc.nunits;
+    const double cy = cost_ns(rt->tasks[y].desc) / rt->tasks[y].desc.nunits;
+    return cx > cy;
+  });
+  std::vector<int64_t> fillp(lbegin);
+  std::vector<size_t> llds(nl, 16);
+  for (int64_t i = 0; i < nt; ++i) {
+    const int64_t t = order[i];
+    const Task &k = rt->tasks[t];
+    desc[t] = k.desc;
+    const int L = level[t];
+    llds[L] = std::max(llds[L], lds_for(k.desc));
+    for (int u = 0; u < k.desc.nunits; ++u)
+      items[fillp[L]++] = ((uint64_t)(uint32_t)t << 32) | (uint32_t)u;
+  }
+  memset(hb + o_cnt, 0, nl * 8);
+  memset(hb + o_info, 0, std::max(nslots_roots, 1) * 8);
+  memset(hb + o_failed, 0, std::max(nslots_roots, 1) * 4);
+  if (trace) {
+    int64_t *tr = (int64_t *)(hb + o_trace);
+    for (int64_t t = 0; t < nt; ++t) { tr[3 * t] = INT64_MAX; tr[3 * t + 1] = 0; tr[3 * t + 2] = -1; }
+  }
+  auto t_build1 = std::chrono::steady_clock::now();
+  rt->last_build_ms = std::chrono::duration<double, std::milli>(t_build1 - t_build0).count();
+
+  hipError_t e = hipMemcpyAsync(rt->arena_dev, rt->arena_host, total, hipMemcpyHostToDevice,
+                                rt->stream);
+  if (e != hipSuccess) { drop(); return fail_hip(e, "hipMemcpyAsync(graph)"); }
+  char *db = (char *)rt->arena_dev;
+  int max_workers = 0;
+  for (int64_t L = 0; L < nl; ++L) {
+    LevelArgs a;
+    a.desc = (const TaskDesc *)(db + o_desc);
+    a.items = (const uint64_t *)(db + o_items);
+    a.begin = lbegin[L];
+    a.count = lcount[L];
+    a.counter = (unsigned long long *)(db + o_cnt) + L;
+    a.failed = (int32_t *)(db + o_failed);
+    a.info = (int64_t *)(db + o_info);
+    a.trace = trace ? (int64_t *)(db + o_trace) : nullptr;
+    int per_cu = 1;
+    dcx_level_occupancy(llds[L], &per_cu);
+    int workers = rt->cfg.workers > 0 ? rt->cfg.workers : rt->num_cus * std::max(1, per_cu);
+    workers = (int)std::min<int64_t>(workers, lcount[L]);
+    if (workers <= 0) continue;
+    max_workers = std::max(max_workers, workers);
+    int le = dcx_launch_level(a, workers, llds[L], rt->stream);
+    if (le != 0) {
+      fail_hip((hipError_t)le, "level launch");
+      drop();
+      return -EIO;
+    }
+  }
+  Inflight &f = rt->fl;
+  f.tail_off = o_tail;
+  f.tail_bytes = tail_end - o_tail;
+  f.status_off = -1;
+  f.info_off = o_info;
+  f.trace_off = o_trace;
+  f.ntasks = nt;
+  f.slot_roots = rt->slot_roots;
+  f.slot_factor = rt->slot_factor;
+  f.kinds.resize(nt);
+  for (int64_t t = 0; t < nt; ++t) f.kinds[t] = rt->tasks[t].desc.kind;
+  rt->inflight = true;
+  rt->last_units = total_units;
+  rt->last_workers = max_workers;
+  rt->last_levels = nl;
+  drop();
+  return 0;
+}
+
+extern "C" int dc_wait_all(dc_runtime *rt) {
+  if (!rt) return -EINVAL;
+  int e = dc_flush(rt);
+  if (e) return e;
+  return finalize(rt);
+}
+
+extern "C" const char *dc_strerror(int err) {
+  switch (err) {
+    case 0: return "success";
+    case -EINVAL: return "invalid argument (arity, access mode, dtype or shape)";
+    case -ENOENT: return "unregistered handle or pointer";
+    case -EBUSY: return "handle busy (partitioned or referenced by pending tasks)";
+    case -ENOMEM: return "out of memory or capacity";
+    case -ENODEV: return "no device: host-only runtime cannot execute tasks";
+    case -ETIMEDOUT: return "executor watchdog expired";
+    case -EIO: return "HIP runtime error";
+    default: return "unknown error";
+  }
+}
+
+// Runtime diagnostics used by the Python layer and the benchmark.
+extern "C" int dc_last_launch(dc_runtime *rt, double *build_ms, int64_t *units, int32_t *workers) {
+  if (!rt) return -EINVAL;
+  (void)rt->last_levels;
+  if (build_ms) *build_ms = rt->last_build_ms;
+  if (units) *units = rt->last_units;
+  if (workers) *workers = rt->last_workers;
+  return 0;
+}

@@ -1,0 +1,85 @@
+// Internal host-side state of a dagchol runtime.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/dagchol.h"
+#include "exec_abi.h"
+
+enum HandleKind { HK_VECTOR = 0, HK_MATRIX = 1 };
+
+struct Handle {
+  int kind = HK_MATRIX;
+  void *ptr = nullptr;
+  int64_t rows = 0, cols = 0, ld = 1;
+  int dtype = DC_F64;
+  dc_handle parent = 0;            // 0 for a registered (top-level) handle
+  int64_t ti = 0, tj = 0;          // tile coordinates in the parent
+  int64_t row_off = 0;             // first row in the top-level matrix
+  bool alive = false;
+  bool partitioned = false;
+  int64_t tile = 0, trows = 0, tcols = 0;
+  std::vector<dc_handle> tiles;
+  // dependency-inference state for the graph being built
+  int64_t last_writer = -1;
+  std::vector<int64_t> readers;
+  int pending = 0;
+  // numerical status of the last factorisation (top-level handles)
+  int64_t info = 0;
+};
+
+struct Task {
+  dcx::TaskDesc desc;
+  std::vector<int64_t> preds;
+  int64_t nwar = 0;
+  int prio = 0;
+};
+
+struct Inflight {
+  int64_t tail_off = 0, tail_bytes = 0, status_off = 0, info_off = 0, trace_off = 0;
+  int64_t ntasks = 0;
+  std::vector<dc_handle> slot_roots;
+  std::vector<char> slot_factor;   // slot has a POTRF task in the graph
+  std::vector<int32_t> kinds;
+};
+
+struct dc_runtime {
+  dc_config cfg{};
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  int num_cus = 0;
+  int default_workers = 1;
+  int wall_clock_khz = 100000;
+
+  std::vector<Handle> handles;                 // id - 1 -> handle
+  std::unordered_map<void *, dc_handle> by_ptr;
+  std::vector<dc_handle> touched;              // handles referenced by pending tasks
+  std::vector<Task> tasks;                     // pending graph
+  std::unordered_map<dc_handle, int> slot_of;  // root matrix -> status slot
+  std::vector<dc_handle> slot_roots;
+  std::vector<char> slot_factor;
+
+  void *arena_dev = nullptr;
+  void *arena_host = nullptr;
+  int64_t arena_cap = 0;
+  bool inflight = false;
+  Inflight fl;
+
+  std::vector<int64_t> trace_host;
+  std::vector<int32_t> trace_kind;
+  int64_t trace_t0 = 0;
+
+  double last_build_ms = 0.0;
+  int64_t last_units = 0;
+  int32_t last_workers = 0;
+  int64_t last_levels = 0;
+  std::string last_hip_error;
+
+  Handle *get(dc_handle h);
+  dc_handle root_of(dc_handle h);
+  void reset_graph_state();
+};
