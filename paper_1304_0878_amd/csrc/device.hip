@@ -28,14 +28,23 @@ using namespace dcx;
 namespace {
 
 constexpr int NT = 256;                    // threads per workgroup
-constexpr int KC = 16;                     // K chunk staged per LDS stage
-constexpr int LDS_S = KC + 1;              // padded LDS row stride (doubles)
+constexpr int KC = GEMM_KC;                // K chunk staged per LDS stage
+constexpr int LDS_S = GEMM_LDS_S;          // padded LDS row stride (doubles)
 constexpr int GEMM_STAGE = 2 * GEMM_UNIT * LDS_S;  // A and B of one stage
-constexpr int TRSM_X_DOUBLES = TRSM_LDS_DOUBLES;  // X slab of a TRSM unit
-constexpr int LDS_DOUBLES = 17408;         // 136 KiB of LDS per workgroup
+constexpr int LDS_DOUBLES = GEMM_LDS_DOUBLES;      // 136 KiB of LDS per workgroup
 
 static_assert(2 * GEMM_STAGE <= LDS_DOUBLES, "gemm lds");
-static_assert(TRSM_X_DOUBLES + PANEL * (PANEL + 1) <= LDS_DOUBLES, "trsm lds");
+static_assert(2 * TRSM_ROWS * (MAX_TILE + 2) + PANEL * (PANEL + 1) <= LDS_DOUBLES, "trsm lds");
+static_assert(PANEL * (MAX_TILE + 2) + PANEL * (PANEL + 1) + 8 <= LDS_DOUBLES, "potrf lds");
+
+// Global-memory views of the tile pointers: descriptors hold generic
+// pointers, and loads through them would otherwise be flat loads (which also
+// count against the LDS wait counter and serialize with LDS traffic).
+typedef __attribute__((address_space(1))) double gdouble;
+typedef double dvec2 __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(1))) dvec2 gdvec2;
+typedef __attribute__((address_space(1))) float gfloat;
+template <typename T> using gptr = __attribute__((address_space(1))) T *;
 
 __device__ __forceinline__ double mfma44(double a, double b, double c) {
   return __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, c, 0, 0, 0);
@@ -48,11 +57,13 @@ __device__ __forceinline__ double mfma44(double a, double b, double c) {
 // issues 64 MFMAs (4x4x4, four 4x4 blocks each): A fragment i holds rows
 // 16i..16i+15 (block b = rows 4b..4b+3), B fragment (c, s) holds columns
 // 16c + 4((b+s) mod 4) .. +3 for block b, so the 16 (i, c, s) products of
-// a 16x16 quad cover its 16 4x4 output blocks exactly once.
+// a 16x16 quad cover its 16 4x4 output blocks exactly once.  Operands are
+// staged through LDS in K chunks of 32, double buffered; full interior
+// blocks use 16-byte global loads without bounds checks.
 // lower_only: skip elements above the diagonal (diagonal SYRK blocks).
-__device__ __forceinline__ void gemm_f64_block(double *__restrict__ C, int64_t ldc,
-                               const double *__restrict__ A, int64_t lda,
-                               const double *__restrict__ B, int64_t ldb,
+__device__ __forceinline__ void gemm_f64_block(gdouble *__restrict__ C, int64_t ldc,
+                               const gdouble *__restrict__ A, int64_t lda,
+                               const gdouble *__restrict__ B, int64_t ldb,
                                int M, int N, int K, bool lower_only, double *lds) {
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -71,19 +82,31 @@ __device__ __forceinline__ void gemm_f64_block(double *__restrict__ C, int64_t l
 #pragma unroll
       for (int s = 0; s < 4; ++s) acc[i][c][s] = 0.0;
 
-  // global -> register loader: thread owns rows lrow + 32j, k pair lkp
-  const int lrow = tid >> 3;
-  const int lkp = (tid & 7) * 2;
-  double ra[8], rb[8];
+  // global -> register loader: thread owns rows lrow + 16j, k pair lkp
+  const int lrow = tid >> 4;
+  const int lkp = (tid & 15) * 2;
+  const bool fast = M == GEMM_UNIT && N == GEMM_UNIT && (K % KC) == 0 &&
+                    (((uintptr_t)A | (uintptr_t)B) & 15) == 0 && ((lda | ldb) & 1) == 0;
+  dvec2 ra[8], rb[8];
   auto gload = [&](int k0) {
+    if (fast) {
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int row = lrow + 32 * j;
+      for (int j = 0; j < 8; ++j) {
+        const int row = lrow + 16 * j;
+        ra[j] = *(const gdvec2 *)(A + (int64_t)row * lda + k0 + lkp);
+        rb[j] = *(const gdvec2 *)(B + (int64_t)row * ldb + k0 + lkp);
+      }
+    } else {
 #pragma unroll
-      for (int e = 0; e < 2; ++e) {
-        const int k = k0 + lkp + e;
-        ra[2 * j + e] = (row < M && k < K) ? A[(int64_t)row * lda + k] : 0.0;
-        rb[2 * j + e] = (row < N && k < K) ? B[(int64_t)row * ldb + k] : 0.0;
+      for (int j = 0; j < 8; ++j) {
+        const int row = lrow + 16 * j;
+        const int k = k0 + lkp;
+        const gdouble *ap = A + (int64_t)row * lda + k;
+        const gdouble *bp = B + (int64_t)row * ldb + k;
+        ra[j].x = (row < M && k < K) ? ap[0] : 0.0;
+        ra[j].y = (row < M && k + 1 < K) ? ap[1] : 0.0;
+        rb[j].x = (row < N && k < K) ? bp[0] : 0.0;
+        rb[j].y = (row < N && k + 1 < K) ? bp[1] : 0.0;
       }
     }
   };
@@ -91,12 +114,10 @@ __device__ __forceinline__ void gemm_f64_block(double *__restrict__ C, int64_t l
     double *As = lds + st * GEMM_STAGE;
     double *Bs = As + GEMM_UNIT * LDS_S;
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
-#pragma unroll
-      for (int e = 0; e < 2; ++e) {
-        As[(lrow + 32 * j) * LDS_S + lkp + e] = ra[2 * j + e];
-        Bs[(lrow + 32 * j) * LDS_S + lkp + e] = rb[2 * j + e];
-      }
+    for (int j = 0; j < 8; ++j) {
+      *(dvec2 *)(As + (lrow + 16 * j) * LDS_S + lkp) = ra[j];
+      *(dvec2 *)(Bs + (lrow + 16 * j) * LDS_S + lkp) = rb[j];
+    }
   };
 
   const int nst = (K + KC - 1) / KC;
@@ -139,7 +160,7 @@ __device__ __forceinline__ void gemm_f64_block(double *__restrict__ C, int64_t l
         const int row = 64 * wr + 16 * i + 4 * blk + kq;
         const int col = 64 * wc + 16 * c + 4 * ((blk + s) & 3) + n4;
         if (row < M && col < N && (!lower_only || col <= row)) {
-          double *p = C + (int64_t)row * ldc + col;
+          gdouble *p = C + (int64_t)row * ldc + col;
           *p = *p - acc[i][c][s];
         }
       }
@@ -150,9 +171,9 @@ __device__ __forceinline__ void run_gemm(const TaskDesc &d, int unit, double *ld
   const int qn = (d.n + GEMM_UNIT - 1) / GEMM_UNIT;
   const int p = unit / qn, q = unit % qn;
   const int r0 = p * GEMM_UNIT, c0 = q * GEMM_UNIT;
-  const double *A = (const double *)d.a;
-  const double *B = (const double *)d.b;
-  double *C = (double *)d.c;
+  const gdouble *A = (const gdouble *)d.a;
+  const gdouble *B = (const gdouble *)d.b;
+  gdouble *C = (gdouble *)d.c;
   gemm_f64_block(C + (int64_t)r0 * d.ldc + c0, d.ldc, A + (int64_t)r0 * d.lda, d.lda,
                  B + (int64_t)c0 * d.ldb, d.ldb, min(GEMM_UNIT, d.m - r0),
                  min(GEMM_UNIT, d.n - c0), d.k, false, lds);
@@ -164,8 +185,8 @@ __device__ __forceinline__ void run_syrk(const TaskDesc &d, int unit, double *ld
   while ((p + 1) * (p + 2) / 2 <= unit) ++p;
   const int q = unit - p * (p + 1) / 2;
   const int r0 = p * GEMM_UNIT, c0 = q * GEMM_UNIT;
-  const double *A = (const double *)d.a;
-  double *C = (double *)d.c;
+  const gdouble *A = (const gdouble *)d.a;
+  gdouble *C = (gdouble *)d.c;
   gemm_f64_block(C + (int64_t)r0 * d.ldc + c0, d.ldc, A + (int64_t)r0 * d.lda, d.lda,
                  A + (int64_t)c0 * d.lda, d.lda, min(GEMM_UNIT, d.m - r0),
                  min(GEMM_UNIT, d.m - c0), d.k, p == q, lds);
@@ -173,22 +194,23 @@ __device__ __forceinline__ void run_syrk(const TaskDesc &d, int unit, double *ld
 
 // ------------------------------------------------------------------ TRSM
 //
-// X (m x nb) <- X L^{-T}; unit = R consecutive rows of X held in LDS.
-// For each 16-column block J: (1) X_J -= X_{<J} L_{J,<J}^T with MFMA (wave
-// w: rows 16(w&1).., columns 8(w>>1)..); (2) one thread per row solves the
-// 16x16 lower-triangular system with L_JJ (divisions by the diagonal).
+// X (m x nb) <- X L^{-T}; unit = 16 consecutive rows of X held in LDS.
+// For each 16-column block J: the rows c0..c0+15 of L left of the block are
+// staged in LDS; (1) X_J -= X_{<J} L_{J,<J}^T with MFMA, wave w producing
+// columns 4w..4w+3 for all 16 rows; (2) one thread per row solves the 16x16
+// lower-triangular system with L_JJ (divisions by the diagonal).
 __device__ __forceinline__ void run_trsm(const TaskDesc &d, int unit, double *lds) {
   const int nb = d.n;
-  const int R = trsm_rows(nb);
-  const int r0 = unit * R;
-  const int rows = min(R, d.m - r0);
-  const int ldx = nb + 1;
-  const double *L = (const double *)d.a;
+  const int r0 = unit * TRSM_ROWS;
+  const int rows = min(TRSM_ROWS, d.m - r0);
+  const int XS = panel_stride(nb);
+  const gdouble *L = (const gdouble *)d.a;
   const int64_t ldl = d.lda;
-  double *X = (double *)d.c + (int64_t)r0 * d.ldc;
+  gdouble *X = (gdouble *)d.c + (int64_t)r0 * d.ldc;
   const int64_t ldc = d.ldc;
-  double *Xs = lds;
-  double *Ljj = lds + R * ldx;            // right after the X slab
+  double *Xs = lds;                          // 16 x XS
+  double *Lp = lds + TRSM_ROWS * XS;         // 16 x XS
+  double *Ljj = Lp + TRSM_ROWS * XS;         // 16 x 17
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int w = tid >> 6;
@@ -197,50 +219,39 @@ __device__ __forceinline__ void run_trsm(const TaskDesc &d, int unit, double *ld
   const int kq = lane >> 4;
   const int n4 = lane & 3;
 
-  for (int idx = tid; idx < R * nb; idx += NT) {
+  for (int idx = tid; idx < TRSM_ROWS * nb; idx += NT) {
     const int r = idx / nb, c = idx - r * nb;
-    Xs[r * ldx + c] = r < rows ? X[(int64_t)r * ldc + c] : 0.0;
+    Xs[r * XS + c] = r < rows ? X[(int64_t)r * ldc + c] : 0.0;
   }
-  __syncthreads();
-
-  const int rg = w & 1;          // 16-row group of this wave
-  const int half = w >> 1;       // 8-column half of the block
-  const bool active = 16 * rg < R;
   const int nj = (nb + PANEL - 1) / PANEL;
   for (int J = 0; J < nj; ++J) {
     const int c0 = PANEL * J;
     const int wj = min(PANEL, nb - c0);
-    // stage L_JJ (lower part) for the triangular step
+    for (int idx = tid; idx < PANEL * c0; idx += NT) {
+      const int r = idx / c0, k = idx - r * c0;
+      Lp[r * XS + k] = r < wj ? L[(int64_t)(c0 + r) * ldl + k] : 0.0;
+    }
     for (int idx = tid; idx < PANEL * PANEL; idx += NT) {
       const int i = idx / PANEL, j = idx % PANEL;
       Ljj[i * (PANEL + 1) + j] = (i < wj && j <= i) ? L[(int64_t)(c0 + i) * ldl + c0 + j] : 0.0;
     }
-    if (active && c0 > 0) {
-      double acc0 = 0.0, acc1 = 0.0;
-      const int colA = 8 * half + 4 * (blk & 1) + n4;        // s = 0
-      const int colB = 8 * half + 4 * ((blk + 1) & 1) + n4;  // s = 1
-      const bool okA = colA < wj, okB = colB < wj;
-      const double *LA = L + (int64_t)(c0 + colA) * ldl;
-      const double *LB = L + (int64_t)(c0 + colB) * ldl;
-      const double *xr = Xs + (16 * rg + l16) * ldx;
-      for (int k0 = 0; k0 < c0; k0 += 4) {
-        const int k = k0 + kq;
-        const double a = xr[k];
-        const double b0 = okA ? LA[k] : 0.0;
-        const double b1 = okB ? LB[k] : 0.0;
-        acc0 = mfma44(a, b0, acc0);
-        acc1 = mfma44(a, b1, acc1);
+    __syncthreads();
+    if (c0 > 0) {
+      double acc = 0.0;
+      const double *xa = Xs + l16 * XS + kq;
+      const double *lb = Lp + (4 * w + n4) * XS + kq;
+      for (int k0 = 0; k0 < c0; k0 += 16) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc = mfma44(xa[k0 + 4 * j], lb[k0 + 4 * j], acc);
       }
-      const int row = 16 * rg + 4 * blk + kq;
-      if (row < R) {
-        if (okA) Xs[row * ldx + c0 + colA] -= acc0;
-        if (okB) Xs[row * ldx + c0 + colB] -= acc1;
-      }
+      const int row = 4 * blk + kq;
+      const int col = 4 * w + n4;
+      if (col < wj) Xs[row * XS + c0 + col] -= acc;
     }
     __syncthreads();
     if (tid < rows) {
       double v[PANEL];
-      double *xr = Xs + tid * ldx + c0;
+      double *xr = Xs + tid * XS + c0;
 #pragma unroll
       for (int j = 0; j < PANEL; ++j) v[j] = j < wj ? xr[j] : 0.0;
 #pragma unroll
@@ -260,21 +271,24 @@ __device__ __forceinline__ void run_trsm(const TaskDesc &d, int unit, double *ld
   }
   for (int idx = tid; idx < rows * nb; idx += NT) {
     const int r = idx / nb, c = idx - r * nb;
-    X[(int64_t)r * ldc + c] = Xs[r * ldx + c];
+    X[(int64_t)r * ldc + c] = Xs[r * XS + c];
   }
 }
 
 // ----------------------------------------------------------------- POTRF
 //
 // D (nb x nb, lower) = L L^T in place.  Left-looking over 16-column panels:
-// (1) D[c0:, c0:c0+16] -= D[c0:, :c0] D[c0:c0+16, :c0]^T with MFMA (16-row
-// groups spread over the waves); (2) column by column: the owner of the
-// pivot row forms the pivot, takes its square root (or reports breakdown),
-// publishes its row in LDS, and every thread divides its rows' entries.
-// Returns 0 or the 1-based local column of the first non-positive pivot.
+// (1) D[c0:, c0:c0+16] -= D[c0:, :c0] D[c0:c0+16, :c0]^T with MFMA: the 16
+// pivot rows are staged in LDS, each wave takes every fourth 16-row group
+// and keeps up to eight groups' accumulators, the next 16 columns of its
+// rows being loaded while the current ones are multiplied; (2) column by
+// column: the owner of the pivot row forms the pivot, takes its square root
+// (or reports breakdown), publishes its row in LDS, and every thread divides
+// its rows' entries.  Returns 0 or the 1-based local column of the first
+// non-positive pivot.
 __device__ __forceinline__ int run_potrf(const TaskDesc &d, double *lds) {
   const int nb = d.m;
-  double *D = (double *)d.c;
+  gdouble *D = (gdouble *)d.c;
   const int64_t ldd = d.ldc;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -283,9 +297,12 @@ __device__ __forceinline__ int run_potrf(const TaskDesc &d, double *lds) {
   const int blk = l16 >> 2;
   const int kq = lane >> 4;
   const int n4 = lane & 3;
-  double *Ds = lds;                          // 16 x 17: published pivot rows
-  int *flag = (int *)(lds + PANEL * (PANEL + 1));
+  const int BS = panel_stride(nb);
+  double *Bp = lds;                          // 16 x BS: pivot rows left of the panel
+  double *Ds = Bp + PANEL * BS;              // 16 x 17: published pivot rows
+  int *flag = (int *)(Ds + PANEL * (PANEL + 1));
   constexpr int RPT = MAX_TILE / NT;         // row slots per thread
+  constexpr int GQ = MAX_TILE / PANEL / 4;   // row groups per wave
 
   const int nj = (nb + PANEL - 1) / PANEL;
   int bad = 0;
@@ -294,33 +311,64 @@ __device__ __forceinline__ int run_potrf(const TaskDesc &d, double *lds) {
     const int wj = min(PANEL, nb - c0);
     const int nrows = nb - c0;
     if (c0 > 0) {
+      for (int idx = tid; idx < PANEL * c0; idx += NT) {
+        const int r = idx / c0, k = idx - r * c0;
+        Bp[r * BS + k] = r < wj ? D[(int64_t)(c0 + r) * ldd + k] : 0.0;
+      }
+      __syncthreads();
       const int ngroups = (nrows + 15) / 16;
-      for (int g = w; g < ngroups; g += 4) {
-        double acc[4] = {0.0, 0.0, 0.0, 0.0};
-        const int arow = c0 + 16 * g + l16;
-        const bool aok = arow < nb;
-        const double *ap = D + (int64_t)(aok ? arow : c0) * ldd;
-        const double *bp[4];
-        bool bok[4];
+      double acc[GQ][4];
+      double an[GQ][4];
+      const gdouble *ap[GQ];
+      bool aok[GQ];
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-          const int col = 4 * ((blk + s) & 3) + n4;
-          bok[s] = col < wj;
-          bp[s] = D + (int64_t)(c0 + (bok[s] ? col : 0)) * ldd;
+      for (int q = 0; q < GQ; ++q) {
+        const int row = c0 + 16 * (w + 4 * q) + l16;
+        aok[q] = row < nb;
+        ap[q] = D + (int64_t)(aok[q] ? row : c0) * ldd + kq;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) acc[q][s] = 0.0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) an[q][j] = aok[q] ? ap[q][4 * j] : 0.0;
+      }
+      for (int k0 = 0; k0 < c0; k0 += 16) {
+        double ac[GQ][4];
+#pragma unroll
+        for (int q = 0; q < GQ; ++q)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) ac[q][j] = an[q][j];
+        if (k0 + 16 < c0) {
+#pragma unroll
+          for (int q = 0; q < GQ; ++q)
+            if (w + 4 * q < ngroups) {
+#pragma unroll
+              for (int j = 0; j < 4; ++j) an[q][j] = aok[q] ? ap[q][k0 + 16 + 4 * j] : 0.0;
+            }
         }
-        for (int k0 = 0; k0 < c0; k0 += 4) {
-          const int k = k0 + kq;
-          const double a = aok ? ap[k] : 0.0;
 #pragma unroll
-          for (int s = 0; s < 4; ++s) acc[s] = mfma44(a, bok[s] ? bp[s][k] : 0.0, acc[s]);
+        for (int j = 0; j < 4; ++j) {
+          double b[4];
+#pragma unroll
+          for (int s = 0; s < 4; ++s) b[s] = Bp[(4 * ((blk + s) & 3) + n4) * BS + k0 + 4 * j + kq];
+#pragma unroll
+          for (int q = 0; q < GQ; ++q)
+            if (w + 4 * q < ngroups) {
+#pragma unroll
+              for (int s = 0; s < 4; ++s) acc[q][s] = mfma44(ac[q][j], b[s], acc[q][s]);
+            }
         }
-        const int row = c0 + 16 * g + 4 * blk + kq;
+      }
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-          const int col = 4 * ((blk + s) & 3) + n4;
-          if (row < nb && col < wj && c0 + col <= row) {
-            double *p = D + (int64_t)row * ldd + c0 + col;
-            *p = *p - acc[s];
+      for (int q = 0; q < GQ; ++q) {
+        if (w + 4 * q < ngroups) {
+          const int row = c0 + 16 * (w + 4 * q) + 4 * blk + kq;
+#pragma unroll
+          for (int s = 0; s < 4; ++s) {
+            const int col = 4 * ((blk + s) & 3) + n4;
+            if (row < nb && col < wj && c0 + col <= row) {
+              gdouble *p = D + (int64_t)row * ldd + c0 + col;
+              *p = *p - acc[q][s];
+            }
           }
         }
       }
@@ -390,9 +438,9 @@ __device__ __forceinline__ int run_potrf(const TaskDesc &d, double *lds) {
 // through the 16x16 diagonal block.
 template <typename TL>
 __device__ __forceinline__ void run_trsm_l(const TaskDesc &d, double *lds) {
-  const TL *L = (const TL *)d.a;
+  const gptr<const TL> L = (const gptr<const TL>)d.a;
   const int64_t ldl = d.lda;
-  double *Bm = (double *)d.c;
+  gdouble *Bm = (gdouble *)d.c;
   const int64_t ldb = d.ldc;
   const int nb = d.m, r = d.n;
   const int tid = threadIdx.x;
@@ -408,10 +456,10 @@ __device__ __forceinline__ void run_trsm_l(const TaskDesc &d, double *lds) {
 #pragma unroll
         for (int c = 0; c < 16; ++c) acc[c] = 0.0;
         if (ri < h) {
-          const TL *lr = L + (int64_t)(i0 + ri) * ldl;
+          gptr<const TL> lr = L + (int64_t)(i0 + ri) * ldl;
           for (int p = sl; p < i0; p += 16) {
             const double lv = (double)lr[p];
-            const double *bp = Bm + (int64_t)p * ldb + c0;
+            const gdouble *bp = Bm + (int64_t)p * ldb + c0;
 #pragma unroll
             for (int c = 0; c < 16; ++c)
               if (c < rc) acc[c] += lv * bp[c];
@@ -435,7 +483,7 @@ __device__ __forceinline__ void run_trsm_l(const TaskDesc &d, double *lds) {
         for (int i = 0; i < 16; ++i) {
           if (i < h) {
             double t = Bm[(int64_t)(i0 + i) * ldb + c0 + c] - red[i * 16 + c];
-            const TL *lr = L + (int64_t)(i0 + i) * ldl + i0;
+            gptr<const TL> lr = L + (int64_t)(i0 + i) * ldl + i0;
 #pragma unroll
             for (int p = 0; p < i; ++p) t = t - (double)lr[p] * y[p];
             y[i] = t / (double)lr[i];
@@ -452,9 +500,9 @@ __device__ __forceinline__ void run_trsm_l(const TaskDesc &d, double *lds) {
 // rows uses columns of L (row p of L gives L^T's column p).
 template <typename TL>
 __device__ __forceinline__ void run_trsm_lt(const TaskDesc &d, double *lds) {
-  const TL *L = (const TL *)d.a;
+  const gptr<const TL> L = (const gptr<const TL>)d.a;
   const int64_t ldl = d.lda;
-  double *Bm = (double *)d.c;
+  gdouble *Bm = (gdouble *)d.c;
   const int64_t ldb = d.ldc;
   const int nb = d.m, r = d.n;
   const int tid = threadIdx.x;
@@ -474,7 +522,7 @@ __device__ __forceinline__ void run_trsm_lt(const TaskDesc &d, double *lds) {
         if (ci < h) {
           for (int p = i0 + 16 + sl; p < nb; p += 16) {
             const double lv = (double)L[(int64_t)p * ldl + i0 + ci];
-            const double *bp = Bm + (int64_t)p * ldb + c0;
+            const gdouble *bp = Bm + (int64_t)p * ldb + c0;
 #pragma unroll
             for (int c = 0; c < 16; ++c)
               if (c < rc) acc[c] += lv * bp[c];
@@ -515,23 +563,23 @@ __device__ __forceinline__ void run_trsm_lt(const TaskDesc &d, double *lds) {
 // 16 rows, lanes split the kb sum, a fixed butterfly reduces across lanes.
 template <typename TL>
 __device__ __forceinline__ void run_gemm_rhs_n(const TaskDesc &d, int unit) {
-  const TL *L = (const TL *)d.a;
-  const double *Y = (const double *)d.b;
-  double *Bm = (double *)d.c;
+  const gptr<const TL> L = (const gptr<const TL>)d.a;
+  const gdouble *Y = (const gdouble *)d.b;
+  gdouble *Bm = (gdouble *)d.c;
   const int m = d.m, r = d.n, kb = d.k;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int i0 = unit * ROW_UNIT;
   for (int ii = w; ii < ROW_UNIT; ii += 4) {
     const int i = i0 + ii;
     if (i >= m) break;
-    const TL *lr = L + (int64_t)i * d.lda;
+    gptr<const TL> lr = L + (int64_t)i * d.lda;
     for (int c0 = 0; c0 < r; c0 += 8) {
       double acc[8];
 #pragma unroll
       for (int c = 0; c < 8; ++c) acc[c] = 0.0;
       for (int p = lane; p < kb; p += 64) {
         const double lv = (double)lr[p];
-        const double *yp = Y + (int64_t)p * d.ldb + c0;
+        const gdouble *yp = Y + (int64_t)p * d.ldb + c0;
 #pragma unroll
         for (int c = 0; c < 8; ++c)
           if (c0 + c < r) acc[c] += lv * yp[c];
@@ -548,7 +596,7 @@ __device__ __forceinline__ void run_gemm_rhs_n(const TaskDesc &d, int unit) {
 #pragma unroll
         for (int c = 1; c < 8; ++c)
           if (lane == c) v = acc[c];
-        double *bp = Bm + (int64_t)i * d.ldc + c0 + lane;
+        gdouble *bp = Bm + (int64_t)i * d.ldc + c0 + lane;
         *bp = *bp - v;
       }
     }
@@ -559,9 +607,9 @@ __device__ __forceinline__ void run_gemm_rhs_n(const TaskDesc &d, int unit) {
 // slices of the kb sum per row, summed in a fixed order.
 template <typename TL>
 __device__ __forceinline__ void run_gemm_rhs_t(const TaskDesc &d, int unit, double *lds) {
-  const TL *L = (const TL *)d.a;
-  const double *Y = (const double *)d.b;
-  double *Bm = (double *)d.c;
+  const gptr<const TL> L = (const gptr<const TL>)d.a;
+  const gdouble *Y = (const gdouble *)d.b;
+  gdouble *Bm = (gdouble *)d.c;
   const int m = d.m, r = d.n, kb = d.k;
   const int tid = threadIdx.x;
   const int ii = tid & 63, sl = tid >> 6;
@@ -574,7 +622,7 @@ __device__ __forceinline__ void run_gemm_rhs_t(const TaskDesc &d, int unit, doub
     if (i < m) {
       for (int p = sl; p < kb; p += 4) {
         const double lv = (double)L[(int64_t)p * d.lda + i];
-        const double *yp = Y + (int64_t)p * d.ldb + c0;
+        const gdouble *yp = Y + (int64_t)p * d.ldb + c0;
 #pragma unroll
         for (int c = 0; c < 8; ++c)
           if (c0 + c < r) acc[c] += lv * yp[c];
@@ -589,7 +637,7 @@ __device__ __forceinline__ void run_gemm_rhs_t(const TaskDesc &d, int unit, doub
         if (c0 + c < r) {
           const double s = ((part[(0 * 64 + ii) * 8 + c] + part[(1 * 64 + ii) * 8 + c]) +
                             part[(2 * 64 + ii) * 8 + c]) + part[(3 * 64 + ii) * 8 + c];
-          double *bp = Bm + (int64_t)i * d.ldc + c0 + c;
+          gdouble *bp = Bm + (int64_t)i * d.ldc + c0 + c;
           *bp = *bp - s;
         }
       }
@@ -602,7 +650,7 @@ __device__ __forceinline__ void run_gemm_rhs_t(const TaskDesc &d, int unit, doub
 
 // The paper's scale_vector task: x[i] *= factor (binary32).
 __device__ __forceinline__ void run_scal(const TaskDesc &d, int unit) {
-  float *x = (float *)d.c;
+  gfloat *x = (gfloat *)d.c;
   const float f = (float)d.alpha;
   const int64_t base = (int64_t)unit * 4096;
   for (int64_t i = base + threadIdx.x; i < base + 4096 && i < d.m; i += NT) x[i] = x[i] * f;
@@ -637,8 +685,8 @@ __device__ __forceinline__ void run_cast(const TaskDesc &d, int unit) {
 __device__ __forceinline__ void run_axpy(const TaskDesc &d, int unit) {
   const int r0 = unit * ROW_UNIT;
   const int rows = min(ROW_UNIT, d.m - r0);
-  const double *D = (const double *)d.a;
-  double *X = (double *)d.c;
+  const gdouble *D = (const gdouble *)d.a;
+  gdouble *X = (gdouble *)d.c;
   for (int64_t idx = threadIdx.x; idx < (int64_t)rows * d.n; idx += NT) {
     const int64_t r = r0 + idx / d.n, c = idx % d.n;
     X[r * d.ldc + c] = X[r * d.ldc + c] + D[r * d.lda + c];
@@ -650,10 +698,10 @@ __device__ __forceinline__ void run_axpy(const TaskDesc &d, int unit) {
 // rows below the unit; each wave sums a slice and the slices are added in a
 // fixed order.
 __device__ __forceinline__ void run_resid(const TaskDesc &d, int unit, double *lds) {
-  const double *A = (const double *)d.a;
-  const double *X = (const double *)d.b;
-  const double *Bm = (const double *)d.d;
-  double *R = (double *)d.c;
+  const gdouble *A = (const gdouble *)d.a;
+  const gdouble *X = (const gdouble *)d.b;
+  const gdouble *Bm = (const gdouble *)d.d;
+  gdouble *R = (gdouble *)d.c;
   const int n = d.m, r = d.n;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int i0 = unit * ROW_UNIT;
@@ -668,10 +716,10 @@ __device__ __forceinline__ void run_resid(const TaskDesc &d, int unit, double *l
 #pragma unroll
       for (int c = 0; c < 8; ++c) acc[c] = 0.0;
       if (i < n) {
-        const double *ar = A + (int64_t)i * d.lda;
+        const gdouble *ar = A + (int64_t)i * d.lda;
         for (int j = lane; j <= i; j += 64) {
           const double av = ar[j];
-          const double *xp = X + (int64_t)j * d.ldb + c0;
+          const gdouble *xp = X + (int64_t)j * d.ldb + c0;
 #pragma unroll
           for (int c = 0; c < 8; ++c)
             if (c0 + c < r) acc[c] += av * xp[c];
@@ -696,7 +744,7 @@ __device__ __forceinline__ void run_resid(const TaskDesc &d, int unit, double *l
         for (int j = i0 + 1 + w; j < n; j += 4) {
           if (j > i) {
             const double av = A[(int64_t)j * d.lda + i];
-            const double *xp = X + (int64_t)j * d.ldb + c0;
+            const gdouble *xp = X + (int64_t)j * d.ldb + c0;
 #pragma unroll
             for (int c = 0; c < 8; ++c)
               if (c0 + c < r) acc[c] += av * xp[c];

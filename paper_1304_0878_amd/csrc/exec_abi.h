@@ -23,15 +23,26 @@ constexpr int ROW_UNIT = 64;
 // Column block of POTRF and TRSM.
 constexpr int PANEL = 16;
 // Largest tile edge the POTRF and TRSM units accept.
-constexpr int MAX_TILE = 1024;
-// LDS budget (doubles) of the TRSM row panel.
-constexpr int TRSM_LDS_DOUBLES = 16896;
+constexpr int MAX_TILE = 512;
+// Rows of X one TRSM unit keeps in LDS.
+constexpr int TRSM_ROWS = 16;
 
-// Rows of X one TRSM unit keeps in LDS for a tile of width nb.
-__host__ __device__ inline int trsm_rows(int nb) {
-  int r = 32;
-  while (r > 1 && r * (nb + 1) > TRSM_LDS_DOUBLES) r >>= 1;
-  return r;
+__host__ __device__ inline int trsm_rows(int) { return TRSM_ROWS; }
+
+// Padded LDS row stride (doubles) for panels of up to nb columns: a
+// multiple of 32 plus 2, so that 16 consecutive rows read at one column
+// fall in distinct bank pairs.
+__host__ __device__ inline int panel_stride(int nb) { return (nb + 31) / 32 * 32 + 2; }
+
+// LDS (doubles) each unit kind needs.
+constexpr int GEMM_KC = 32;
+constexpr int GEMM_LDS_S = GEMM_KC + 2;
+constexpr int GEMM_LDS_DOUBLES = 2 * 2 * GEMM_UNIT * GEMM_LDS_S;
+__host__ __device__ inline int trsm_lds_doubles(int nb) {
+  return 2 * TRSM_ROWS * panel_stride(nb) + PANEL * (PANEL + 1);
+}
+__host__ __device__ inline int potrf_lds_doubles(int nb) {
+  return PANEL * panel_stride(nb) + PANEL * (PANEL + 1) + 8;
 }
 
 // One task, as the executor reads it (128 bytes).

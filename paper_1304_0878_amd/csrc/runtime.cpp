@@ -616,9 +616,9 @@ static int finalize(dc_runtime *rt) {
 // LDS bytes the level kernel needs for a unit of this task.
 static size_t lds_for(const TaskDesc &d) {
   switch (d.kind) {
-    case K_GEMM: case K_SYRK: return (size_t)2 * 2 * GEMM_UNIT * 17 * 8;
-    case K_TRSM: return (size_t)(trsm_rows(d.n) * (d.n + 1) + PANEL * (PANEL + 1)) * 8;
-    case K_POTRF: return (size_t)(PANEL * (PANEL + 1) + 8) * 8;
+    case K_GEMM: case K_SYRK: return (size_t)GEMM_LDS_DOUBLES * 8;
+    case K_TRSM: return (size_t)trsm_lds_doubles(d.n) * 8;
+    case K_POTRF: return (size_t)potrf_lds_doubles(d.m) * 8;
     case K_TRSM_L: case K_TRSM_LT: return (size_t)(16 * 16 * 16 + 16 * 16) * 8;
     case K_GEMM_RHS_T: return (size_t)(4 * 64 * 8) * 8;
     case K_RESID: return (size_t)(2 * 64 * 8 + 4 * 64 * 8) * 8;
