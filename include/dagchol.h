@@ -89,14 +89,20 @@ typedef enum { DC_F64 = 0, DC_F32 = 1, DC_BF16 = 2 } dc_dtype;
  *   DC_RESID      (A:R, X:R, B:R, R:W)  R <- B - A X, A symmetric given by
  *                                   its lower triangle, FP64.
  *   DC_AXPY       (D:R, X:RW)       X <- X + D, FP64 matrices of one shape.
- * Tiles may be FP64, or (mixed precision) FP32 for TRSM, SYRK and GEMM
- * inputs and BF16 for SYRK/GEMM inputs, as the dtypes of the handles say.
+ *   DC_TRSM_CAST  (L:R, X:RW, S:W)  TRSM on an FP32 tile X that also writes
+ *                                   S = BF16(X) (round to nearest even).
+ * Precisions (the dtypes of the handles select the kernel):
+ *   POTRF: FP64.  TRSM: L FP64, X FP64 or FP32 (FP64 arithmetic, FP32 tiles
+ *   rounded on store).  SYRK/GEMM: FP64 inputs update FP64 tiles with FP64
+ *   MFMA; FP32 or BF16 inputs (both operands of one dtype) multiply with
+ *   FP32 accumulation and the product is subtracted from an FP32 or FP64
+ *   tile.  Solve tasks: B FP64, L FP64 or FP32, FP64 arithmetic.
  */
 typedef enum {
   DC_POTRF = 0, DC_TRSM = 1, DC_SYRK = 2, DC_GEMM = 3,
   DC_TRSM_L = 4, DC_GEMM_RHS_N = 5, DC_TRSM_LT = 6, DC_GEMM_RHS_T = 7,
-  DC_SCAL = 8, DC_CAST = 9, DC_RESID = 10, DC_AXPY = 11,
-  DC_NUM_KINDS = 12
+  DC_SCAL = 8, DC_CAST = 9, DC_RESID = 10, DC_AXPY = 11, DC_TRSM_CAST = 12,
+  DC_NUM_KINDS = 13
 } dc_kind;
 
 typedef struct {
@@ -266,6 +272,76 @@ typedef struct {
 int dc_posv_ir(dc_runtime *rt, dc_handle A, dc_handle B, dc_handle X,
                int64_t tile, dc_dtype upd, double tol, int maxit,
                dc_ir_report *rep);
+
+/* Batched factorisation and solve: factors each of the count SPD matrices
+ * A[i] (FP64, lower triangle, in place) with tile size tiles[i] (0: the
+ * matrix order, i.e. one POTRF task) and, where B != NULL and B[i] != 0,
+ * solves A[i] X = B[i] in place in B[i].  All tasks of all matrices form one
+ * graph executed by one set of level launches.  info_out (optional) receives
+ * each matrix's status (0 or the 1-based breakdown column).  Errors as for
+ * dc_potrf; on an error no task runs. */
+int dc_potrf_batched(dc_runtime *rt, int64_t count, const dc_handle *A, const dc_handle *B,
+                     const int64_t *tiles, int64_t *info_out);
+
+/* --------------------------------------------------------------- serving */
+
+/* Continuous-batching solve server.  Requests (one SPD system each) are
+ * admitted in arrival order as soon as one of `slots` slots and enough of the
+ * server's device memory pool are free; each admitted request runs on its own
+ * runtime and streams, so the work of requests in different slots overlaps on
+ * the GPU.  Per request: copy of A into the pool, factorisation (FP64
+ * diagonal tiles, off-diagonal updates at precision `upd`), solve and
+ * FP64-residual refinement to ||d||_inf <= tol ||x||_inf per column; a
+ * breakdown or failed refinement restarts the request with FP64 updates.
+ * The server object is driven by one host thread. */
+typedef struct dc_server dc_server;
+
+typedef struct {
+  int device;          /* HIP device ordinal */
+  int slots;           /* concurrent requests (1..64) */
+  size_t pool_bytes;   /* device memory the server allocates for workspaces */
+  int64_t tile;        /* tile size of the factorisations (<= 512) */
+  int upd;             /* dc_dtype of the trailing updates */
+  double tol;          /* refinement stopping threshold */
+  int maxit;           /* refinement steps before giving up */
+} dc_server_config;
+
+typedef struct {
+  int64_t n, r;        /* order and right-hand-side count */
+  const double *A;     /* device, n x n row-major FP64 (lower triangle read);
+                          must stay valid until the request completes */
+  const double *B;     /* device, n x r row-major FP64 */
+  double *X;           /* device, n x r row-major FP64: the solution */
+  double arrival;      /* arrival time in dc_server_now's clock (seconds) */
+} dc_request;
+
+typedef struct {
+  int64_t id;          /* id returned by dc_server_submit */
+  int status;          /* 0, or a negative errno if the request failed */
+  int64_t info;        /* breakdown column of the (FP64) factorisation, or 0 */
+  int converged, iterations, final_prec, restarts;
+  double last_update;  /* ||d||_inf / ||x||_inf at the last step */
+  double arrival, admitted, completed;   /* dc_server_now clock, seconds */
+} dc_request_result;
+
+/* Defaults: device 0, 4 slots, 64 GiB pool, tile 256, FP32 updates, tol
+ * 1e-12, 30 refinement steps. */
+void dc_server_config_default(dc_server_config *cfg);
+/* Errors: -EINVAL, -ENOMEM (pool allocation), -EIO. */
+int dc_server_create(dc_server **srv, const dc_server_config *cfg);
+/* Waits for the requests in flight, frees everything the server owns. */
+int dc_server_destroy(dc_server *srv);
+/* Seconds since the server was created (the clock of arrival/completion). */
+double dc_server_now(dc_server *srv);
+/* Queues a request; *id receives its id.  Errors: -EINVAL, -ENOMEM (its
+ * FP64 workspace can never fit in the pool). */
+int dc_server_submit(dc_server *srv, const dc_request *req, int64_t *id);
+/* Never blocks: advances every request whose last step finished, admits
+ * waiting requests, and copies up to cap completed results into results;
+ * *ndone receives their number and *active (optional) the number of
+ * requests still queued or running. */
+int dc_server_progress(dc_server *srv, dc_request_result *results, int cap, int *ndone,
+                       int *active);
 
 #ifdef __cplusplus
 }

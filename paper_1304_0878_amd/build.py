@@ -14,13 +14,13 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdagchol.so")
-SOURCES = ["device.hip", "runtime.cpp", "highlevel.cpp", "ir.cpp", "batched.cpp", "serve.cpp"]
+SOURCES = ["device.hip", "gemm_kernel.hip", "runtime.cpp", "highlevel.cpp", "ir.cpp", "batched.cpp", "serve.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    "-Wno-unused-command-line-argument",
+    "-Wno-unused-command-line-argument", "-Wl,--no-undefined",
     "-I", os.path.join(ROOT, "include"),
 ]
 

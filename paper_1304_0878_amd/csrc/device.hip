@@ -9,14 +9,17 @@
 // workgroup ever waits for another: ordering between levels comes from the
 // stream order of the launches.
 //
-// Tile kernels (right-looking tiled Cholesky; the paper's Section 5.1 cites
-// Cholesky as the partitioning idiom):
+// This file holds the panel kernel: every unit kind except the GEMM/SYRK
+// updates, which run in their own kernel (gemm_kernel.hip) concurrently with
+// it.  Tile kernels (right-looking tiled Cholesky; the paper's Section 5.1
+// cites Cholesky as the partitioning idiom):
 //   POTRF  D = L L^T on one diagonal tile (FP64, left-looking 16-column
 //          panels: MFMA panel update, then column-by-column sqrt/divide).
-//   TRSM   X <- X L^{-T} on 32-row slabs of a panel tile kept in LDS.
-//   SYRK   lower(C) -= X X^T, GEMM  C -= X Y^T, on 128x128 output sub-blocks
-//          with the FP64 4x4x4 (4-block) MFMA, operands staged through LDS.
-//   solve  forward/backward substitution and the RHS updates, FP64.
+//   TRSM   X <- X L^{-T} on 16-row slabs of a panel tile kept in LDS (FP64
+//          arithmetic; FP32 tiles are widened on load and rounded on store,
+//          optionally also writing a BF16 copy).
+//   solve  forward/backward substitution and the RHS updates, FP64
+//          arithmetic on FP64 or FP32 factor tiles.
 //
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -28,12 +31,8 @@ using namespace dcx;
 namespace {
 
 constexpr int NT = 256;                    // threads per workgroup
-constexpr int KC = GEMM_KC;                // K chunk staged per LDS stage
-constexpr int LDS_S = GEMM_LDS_S;          // padded LDS row stride (doubles)
-constexpr int GEMM_STAGE = 2 * GEMM_UNIT * LDS_S;  // A and B of one stage
-constexpr int LDS_DOUBLES = GEMM_LDS_DOUBLES;      // 136 KiB of LDS per workgroup
+constexpr int LDS_DOUBLES = PANEL_LDS_DOUBLES;     // largest LDS need of a unit
 
-static_assert(2 * GEMM_STAGE <= LDS_DOUBLES, "gemm lds");
 static_assert(2 * TRSM_ROWS * (MAX_TILE + 2) + PANEL * (PANEL + 1) <= LDS_DOUBLES, "trsm lds");
 static_assert(PANEL * (MAX_TILE + 2) + PANEL * (PANEL + 1) + 8 <= LDS_DOUBLES, "potrf lds");
 
@@ -48,148 +47,6 @@ template <typename T> using gptr = __attribute__((address_space(1))) T *;
 
 __device__ __forceinline__ double mfma44(double a, double b, double c) {
   return __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, c, 0, 0, 0);
-}
-
-// --------------------------------------------------- FP64 GEMM sub-block
-//
-// C[0:M, 0:N] -= A[0:M, 0:K] * B[0:N, 0:K]^T for M, N <= 128, K any.
-// Waves form a 2x2 grid of 64x64 output tiles.  Per K step of 4 a wave
-// issues 64 MFMAs (4x4x4, four 4x4 blocks each): A fragment i holds rows
-// 16i..16i+15 (block b = rows 4b..4b+3), B fragment (c, s) holds columns
-// 16c + 4((b+s) mod 4) .. +3 for block b, so the 16 (i, c, s) products of
-// a 16x16 quad cover its 16 4x4 output blocks exactly once.  Operands are
-// staged through LDS in K chunks of 32, double buffered; full interior
-// blocks use 16-byte global loads without bounds checks.
-// lower_only: skip elements above the diagonal (diagonal SYRK blocks).
-__device__ __forceinline__ void gemm_f64_block(gdouble *__restrict__ C, int64_t ldc,
-                               const gdouble *__restrict__ A, int64_t lda,
-                               const gdouble *__restrict__ B, int64_t ldb,
-                               int M, int N, int K, bool lower_only, double *lds) {
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int w = tid >> 6;
-  const int wr = w >> 1, wc = w & 1;
-  const int l16 = lane & 15;
-  const int blk = l16 >> 2;
-  const int kq = lane >> 4;
-  const int n4 = lane & 3;
-
-  double acc[4][4][4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int c = 0; c < 4; ++c)
-#pragma unroll
-      for (int s = 0; s < 4; ++s) acc[i][c][s] = 0.0;
-
-  // global -> register loader: thread owns rows lrow + 16j, k pair lkp
-  const int lrow = tid >> 4;
-  const int lkp = (tid & 15) * 2;
-  const bool fast = M == GEMM_UNIT && N == GEMM_UNIT && (K % KC) == 0 &&
-                    (((uintptr_t)A | (uintptr_t)B) & 15) == 0 && ((lda | ldb) & 1) == 0;
-  dvec2 ra[8], rb[8];
-  auto gload = [&](int k0) {
-    if (fast) {
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const int row = lrow + 16 * j;
-        ra[j] = *(const gdvec2 *)(A + (int64_t)row * lda + k0 + lkp);
-        rb[j] = *(const gdvec2 *)(B + (int64_t)row * ldb + k0 + lkp);
-      }
-    } else {
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const int row = lrow + 16 * j;
-        const int k = k0 + lkp;
-        const gdouble *ap = A + (int64_t)row * lda + k;
-        const gdouble *bp = B + (int64_t)row * ldb + k;
-        ra[j].x = (row < M && k < K) ? ap[0] : 0.0;
-        ra[j].y = (row < M && k + 1 < K) ? ap[1] : 0.0;
-        rb[j].x = (row < N && k < K) ? bp[0] : 0.0;
-        rb[j].y = (row < N && k + 1 < K) ? bp[1] : 0.0;
-      }
-    }
-  };
-  auto sstore = [&](int st) {
-    double *As = lds + st * GEMM_STAGE;
-    double *Bs = As + GEMM_UNIT * LDS_S;
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      *(dvec2 *)(As + (lrow + 16 * j) * LDS_S + lkp) = ra[j];
-      *(dvec2 *)(Bs + (lrow + 16 * j) * LDS_S + lkp) = rb[j];
-    }
-  };
-
-  const int nst = (K + KC - 1) / KC;
-  gload(0);
-  sstore(0);
-  __syncthreads();
-  for (int st = 0; st < nst; ++st) {
-    const int cur = st & 1;
-    if (st + 1 < nst) gload((st + 1) * KC);
-    const double *As = lds + cur * GEMM_STAGE;
-    const double *Bs = As + GEMM_UNIT * LDS_S;
-#pragma unroll
-    for (int ks = 0; ks < KC / 4; ++ks) {
-      const int kk = 4 * ks + kq;
-      double a[4], b[4][4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] = As[(64 * wr + 16 * i + l16) * LDS_S + kk];
-#pragma unroll
-      for (int c = 0; c < 4; ++c)
-#pragma unroll
-        for (int s = 0; s < 4; ++s)
-          b[c][s] = Bs[(64 * wc + 16 * c + 4 * ((blk + s) & 3) + n4) * LDS_S + kk];
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int c = 0; c < 4; ++c)
-#pragma unroll
-          for (int s = 0; s < 4; ++s) acc[i][c][s] = mfma44(a[i], b[c][s], acc[i][c][s]);
-    }
-    if (st + 1 < nst) sstore(cur ^ 1);
-    __syncthreads();
-  }
-
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int c = 0; c < 4; ++c)
-#pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        const int row = 64 * wr + 16 * i + 4 * blk + kq;
-        const int col = 64 * wc + 16 * c + 4 * ((blk + s) & 3) + n4;
-        if (row < M && col < N && (!lower_only || col <= row)) {
-          gdouble *p = C + (int64_t)row * ldc + col;
-          *p = *p - acc[i][c][s];
-        }
-      }
-}
-
-// GEMM task: C (m x n) -= A (m x k) B (n x k)^T; unit = one 128x128 block.
-__device__ __forceinline__ void run_gemm(const TaskDesc &d, int unit, double *lds) {
-  const int qn = (d.n + GEMM_UNIT - 1) / GEMM_UNIT;
-  const int p = unit / qn, q = unit % qn;
-  const int r0 = p * GEMM_UNIT, c0 = q * GEMM_UNIT;
-  const gdouble *A = (const gdouble *)d.a;
-  const gdouble *B = (const gdouble *)d.b;
-  gdouble *C = (gdouble *)d.c;
-  gemm_f64_block(C + (int64_t)r0 * d.ldc + c0, d.ldc, A + (int64_t)r0 * d.lda, d.lda,
-                 B + (int64_t)c0 * d.ldb, d.ldb, min(GEMM_UNIT, d.m - r0),
-                 min(GEMM_UNIT, d.n - c0), d.k, false, lds);
-}
-
-// SYRK task: lower(C) (m x m) -= A (m x k) A^T; unit = lower block (p, q).
-__device__ __forceinline__ void run_syrk(const TaskDesc &d, int unit, double *lds) {
-  int p = 0;
-  while ((p + 1) * (p + 2) / 2 <= unit) ++p;
-  const int q = unit - p * (p + 1) / 2;
-  const int r0 = p * GEMM_UNIT, c0 = q * GEMM_UNIT;
-  const gdouble *A = (const gdouble *)d.a;
-  gdouble *C = (gdouble *)d.c;
-  gemm_f64_block(C + (int64_t)r0 * d.ldc + c0, d.ldc, A + (int64_t)r0 * d.lda, d.lda,
-                 A + (int64_t)c0 * d.lda, d.lda, min(GEMM_UNIT, d.m - r0),
-                 min(GEMM_UNIT, d.m - c0), d.k, p == q, lds);
 }
 
 // ------------------------------------------------------------------ TRSM
@@ -219,9 +76,12 @@ __device__ __forceinline__ void run_trsm(const TaskDesc &d, int unit, double *ld
   const int kq = lane >> 4;
   const int n4 = lane & 3;
 
+  const bool x32 = d.tc == T_F32;
+  gfloat *X32 = (gfloat *)d.c + (int64_t)r0 * d.ldc;
   for (int idx = tid; idx < TRSM_ROWS * nb; idx += NT) {
     const int r = idx / nb, c = idx - r * nb;
-    Xs[r * XS + c] = r < rows ? X[(int64_t)r * ldc + c] : 0.0;
+    Xs[r * XS + c] = r < rows ? (x32 ? (double)X32[(int64_t)r * ldc + c] : X[(int64_t)r * ldc + c])
+                              : 0.0;
   }
   const int nj = (nb + PANEL - 1) / PANEL;
   for (int J = 0; J < nj; ++J) {
@@ -269,9 +129,17 @@ __device__ __forceinline__ void run_trsm(const TaskDesc &d, int unit, double *ld
     }
     __syncthreads();
   }
+  typedef __attribute__((address_space(1))) __bf16 gbf16;
+  gbf16 *S16 = d.d ? (gbf16 *)d.d + (int64_t)r0 * d.ldd : nullptr;
   for (int idx = tid; idx < rows * nb; idx += NT) {
     const int r = idx / nb, c = idx - r * nb;
-    X[(int64_t)r * ldc + c] = Xs[r * XS + c];
+    if (x32) {
+      const float v = (float)Xs[r * XS + c];
+      X32[(int64_t)r * ldc + c] = v;
+      if (S16) S16[(int64_t)r * d.ldd + c] = (__bf16)v;
+    } else {
+      X[(int64_t)r * ldc + c] = Xs[r * XS + c];
+    }
   }
 }
 
@@ -806,9 +674,7 @@ __global__ void __launch_bounds__(NT, 1) dc_level_kernel(LevelArgs A) {
     const int kind = __builtin_amdgcn_readfirstlane(d.kind);
     if (!skip) {
       switch (kind) {
-        case K_GEMM: run_gemm(d, u, lds); break;
-        case K_SYRK: run_syrk(d, u, lds); break;
-        case K_TRSM: run_trsm(d, u, lds); break;
+        case K_TRSM: case K_TRSM_CAST: run_trsm(d, u, lds); break;
         case K_POTRF: {
           const int bad = run_potrf(d, lds);
           if (bad && tid == 0 && d.matrix >= 0) {

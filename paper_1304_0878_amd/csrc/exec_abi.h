@@ -10,8 +10,8 @@ namespace dcx {
 enum Kind : int32_t {
   K_POTRF = 0, K_TRSM = 1, K_SYRK = 2, K_GEMM = 3,
   K_TRSM_L = 4, K_GEMM_RHS_N = 5, K_TRSM_LT = 6, K_GEMM_RHS_T = 7,
-  K_SCAL = 8, K_CAST = 9, K_RESID = 10, K_AXPY = 11,
-  K_NUM = 12
+  K_SCAL = 8, K_CAST = 9, K_RESID = 10, K_AXPY = 11, K_TRSM_CAST = 12,
+  K_NUM = 13
 };
 
 enum DType : int32_t { T_F64 = 0, T_F32 = 1, T_BF16 = 2 };
@@ -34,16 +34,15 @@ __host__ __device__ inline int trsm_rows(int) { return TRSM_ROWS; }
 // fall in distinct bank pairs.
 __host__ __device__ inline int panel_stride(int nb) { return (nb + 31) / 32 * 32 + 2; }
 
-// LDS (doubles) each unit kind needs.
-constexpr int GEMM_KC = 32;
-constexpr int GEMM_LDS_S = GEMM_KC + 2;
-constexpr int GEMM_LDS_DOUBLES = 2 * 2 * GEMM_UNIT * GEMM_LDS_S;
+// LDS (doubles) each panel-kernel unit kind needs; the largest bounds the
+// panel kernel's dynamic LDS.
 __host__ __device__ inline int trsm_lds_doubles(int nb) {
   return 2 * TRSM_ROWS * panel_stride(nb) + PANEL * (PANEL + 1);
 }
 __host__ __device__ inline int potrf_lds_doubles(int nb) {
   return PANEL * panel_stride(nb) + PANEL * (PANEL + 1) + 8;
 }
+constexpr int PANEL_LDS_DOUBLES = 2 * TRSM_ROWS * (MAX_TILE + 2) + PANEL * (PANEL + 1);
 
 // One task, as the executor reads it (128 bytes).
 struct TaskDesc {
@@ -82,5 +81,9 @@ extern "C++" int dcx_launch_level(const dcx::LevelArgs &args, int workers, size_
                                   void *stream);
 // Allows the level kernel its largest dynamic LDS size.
 extern "C++" int dcx_level_setup(void);
+// Launches the GEMM/SYRK kernel of one level on `stream`.
+extern "C++" int dcx_launch_gemm(const dcx::LevelArgs &args, int workers, void *stream);
+// Allows the GEMM/SYRK kernel its dynamic LDS size.
+extern "C++" int dcx_gemm_setup(void);
 // Workgroups per CU the level kernel keeps resident with lds_bytes of LDS.
 extern "C++" int dcx_level_occupancy(size_t lds_bytes, int *blocks_per_cu);

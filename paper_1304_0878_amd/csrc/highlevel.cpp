@@ -6,6 +6,7 @@
 #include <stdint.h>
 #include <string.h>
 
+#include <algorithm>
 #include <vector>
 
 #include "../../include/dagchol.h"
@@ -60,6 +61,14 @@ int submit3(dc_runtime *rt, dc_kind k, dc_handle a, dc_mode ma, dc_handle c, dc_
 
 }  // namespace
 
+// Drops the pending graph without running it (after a failed submission).
+void dcx_discard_pending(dc_runtime *rt) {
+  rt->reset_graph_state();
+  rt->slot_of.clear();
+  rt->slot_roots.clear();
+  rt->slot_factor.clear();
+}
+
 // Right-looking tiled factorisation on partitioned tiles (submission only).
 // Priorities (Section 5.3's hints): the diagonal factor, the panel TRSMs and
 // the updates of the next panel column come first.
@@ -106,7 +115,8 @@ extern "C" int dc_potrf(dc_runtime *rt, dc_handle A, int64_t tile) {
   if (p->rows == 0) { p->info = 0; return 0; }
   Tiles t;
   TRY(t.open(rt, A, tile));
-  TRY(dcx_submit_potrf_tiles(rt, t.ids, t.tr));
+  int e = dcx_submit_potrf_tiles(rt, t.ids, t.tr);
+  if (e) { dcx_discard_pending(rt); return e; }
   return dc_wait_all(rt);
 }
 
@@ -127,13 +137,57 @@ extern "C" int dc_potrs(dc_runtime *rt, dc_handle L, dc_handle B, int64_t tile) 
   std::vector<dc_handle> rows(tl.tr);
   for (int64_t j = 0; j < tb.tc; ++j) {
     for (int64_t i = 0; i < tl.tr; ++i) rows[i] = tb.at(i, j);
-    TRY(dcx_submit_potrs_tiles(rt, tl.ids, tl.tr, rows));
+    int e = dcx_submit_potrs_tiles(rt, tl.ids, tl.tr, rows);
+    if (e) { dcx_discard_pending(rt); return e; }
   }
   return dc_wait_all(rt);
 }
 
-extern "C" int dc_posv_ir(dc_runtime *rt, dc_handle A, dc_handle B, dc_handle X, int64_t tile,
-                          dc_dtype upd, double tol, int maxit, dc_ir_report *rep) {
-  (void)rt; (void)A; (void)B; (void)X; (void)tile; (void)upd; (void)tol; (void)maxit; (void)rep;
-  return -ENOSYS;
+// Many independent factorisations (and solves) in one graph: one flush, one
+// set of level launches for the whole batch.  tiles[i] == 0 selects the
+// matrix order (a single POTRF task); B[i] == 0 skips the solve.
+extern "C" int dc_potrf_batched(dc_runtime *rt, int64_t count, const dc_handle *A,
+                                const dc_handle *B, const int64_t *tiles, int64_t *info_out) {
+  if (!rt || count < 0 || (count > 0 && (!A || !tiles))) return -EINVAL;
+  for (int64_t i = 0; i < count; ++i) {
+    Handle *p = rt->get(A[i]);
+    if (!p) return -ENOENT;
+    const int64_t tile = tiles[i] > 0 ? std::min(tiles[i], p->rows) : p->rows;
+    if (p->rows != p->cols || p->dtype != DC_F64 || tiles[i] < 0 ||
+        (p->rows > 0 && (tile < 1 || tile > dcx::MAX_TILE)))
+      return -EINVAL;
+    if (p->partitioned) return -EBUSY;
+    if (B && B[i]) {
+      Handle *q = rt->get(B[i]);
+      if (!q) return -ENOENT;
+      if (q->rows != p->rows || q->dtype != DC_F64) return -EINVAL;
+      if (q->partitioned) return -EBUSY;
+    }
+  }
+  int err = dc_wait_all(rt);
+  if (err) return err;
+  std::vector<Tiles> ta(count), tb(count);
+  for (int64_t i = 0; i < count && !err; ++i) {
+    Handle *p = rt->get(A[i]);
+    if (p->rows == 0) continue;
+    const int64_t tile = tiles[i] > 0 ? std::min<int64_t>(tiles[i], p->rows) : p->rows;
+    err = ta[i].open(rt, A[i], tile);
+    if (!err) err = dcx_submit_potrf_tiles(rt, ta[i].ids, ta[i].tr);
+    if (!err && B && B[i] && rt->get(B[i])->cols > 0) {
+      err = tb[i].open(rt, B[i], tile);
+      std::vector<dc_handle> rows(ta[i].tr);
+      for (int64_t j = 0; j < tb[i].tc && !err; ++j) {
+        for (int64_t r = 0; r < ta[i].tr; ++r) rows[r] = tb[i].at(r, j);
+        err = dcx_submit_potrs_tiles(rt, ta[i].ids, ta[i].tr, rows);
+      }
+    }
+  }
+  if (err) {
+    dcx_discard_pending(rt);
+    return err;
+  }
+  err = dc_wait_all(rt);
+  if (info_out)
+    for (int64_t i = 0; i < count; ++i) dc_get_info(rt, A[i], &info_out[i]);
+  return err;
 }

@@ -1,0 +1,256 @@
+// Mixed-precision Cholesky solve with FP64-residual iterative refinement.
+//
+// Only submits tasks through dc_task_submit and waits.  The factor is kept
+// in a runtime-owned workspace: the diagonal tiles in FP64 (POTRF stays
+// FP64), the off-diagonal tiles in FP32 and, for BF16 updates, a BF16 copy
+// of each finished panel tile written by the TRSM.  A stays untouched and is
+// the matrix of the FP64 residual r = b - A x.
+#include <errno.h>
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <vector>
+
+#include "../../include/dagchol.h"
+#include "runtime_internal.h"
+
+int dcx_submit_potrf_tiles(dc_runtime *rt, const std::vector<dc_handle> &A, int64_t T);
+int dcx_submit_potrs_tiles(dc_runtime *rt, const std::vector<dc_handle> &L, int64_t T,
+                           const std::vector<dc_handle> &B);
+
+namespace {
+
+#define TRY(x) do { int e_ = (x); if (e_) return e_; } while (0)
+
+int submit(dc_runtime *rt, dc_kind k, std::initializer_list<dc_handle> h,
+           std::initializer_list<dc_mode> m, int prio, const void *cl = nullptr,
+           size_t cls = 0) {
+  std::vector<dc_handle> hb(h);
+  std::vector<dc_mode> mb(m);
+  return dc_task_submit(rt, k, (int)hb.size(), hb.data(), mb.data(), cl, cls, prio);
+}
+
+struct Scratch {
+  void *ptr = nullptr;
+  size_t bytes = 0;
+  ~Scratch() { if (ptr) hipFree(ptr); }
+  int get(size_t b) {
+    if (b <= bytes) return 0;
+    if (ptr) hipFree(ptr);
+    ptr = nullptr;
+    bytes = 0;
+    if (hipMalloc(&ptr, b) != hipSuccess) { ptr = nullptr; return -ENOMEM; }
+    bytes = b;
+    return 0;
+  }
+};
+
+// Handles registered for one call; all unregistered on scope exit.
+struct Regs {
+  dc_runtime *rt;
+  std::vector<dc_handle> hs;
+  explicit Regs(dc_runtime *r) : rt(r) {}
+  int mat(dc_handle *out, void *p, int64_t rows, int64_t cols, int64_t ld, dc_dtype t,
+          dc_handle status_root) {
+    int e = dc_matrix_register(rt, out, p, rows, cols, ld, t);
+    if (e) return e;
+    hs.push_back(*out);
+    rt->handles[*out - 1].status_root = status_root;
+    return 0;
+  }
+  ~Regs() {
+    for (auto it = hs.rbegin(); it != hs.rend(); ++it) dc_unregister(rt, *it);
+  }
+};
+
+double now_ms() {
+  return std::chrono::duration<double, std::milli>(
+             std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// Submits the factorisation of A (FP64 lower, partitioned tiles At) at update
+// precision upd into the workspace: D[k] FP64 diagonal tiles, W (FP32) and S
+// (BF16) off-diagonal tile handles.  For upd == FP64 the tiles W are FP64.
+int submit_mixed_factor(dc_runtime *rt, int64_t T, int64_t tile, const std::vector<dc_handle> &At,
+                        const std::vector<dc_handle> &D, const std::vector<dc_handle> &W,
+                        const std::vector<dc_handle> &S, dc_dtype upd) {
+  auto a = [&](int64_t i, int64_t j) { return At[i * T + j]; };
+  auto w = [&](int64_t i, int64_t j) { return W[i * T + j]; };
+  auto s = [&](int64_t i, int64_t j) { return S[i * T + j]; };
+  for (int64_t i = 0; i < T; ++i) {
+    TRY(submit(rt, DC_CAST, {a(i, i), D[i]}, {DC_R, DC_W}, 0));
+    for (int64_t j = 0; j < i; ++j)
+      TRY(submit(rt, DC_CAST, {a(i, j), w(i, j)}, {DC_R, DC_W}, j == 0 ? 0 : 1));
+  }
+  const bool bf = upd == DC_BF16;
+  for (int64_t k = 0; k < T; ++k) {
+    const int64_t row0 = k * tile;
+    TRY(submit(rt, DC_POTRF, {D[k]}, {DC_RW}, 0, &row0, sizeof(row0)));
+    for (int64_t i = k + 1; i < T; ++i) {
+      const int pr = i == k + 1 ? 0 : 1;
+      if (bf)
+        TRY(submit(rt, DC_TRSM_CAST, {D[k], w(i, k), s(i, k)}, {DC_R, DC_RW, DC_W}, pr));
+      else
+        TRY(submit(rt, DC_TRSM, {D[k], w(i, k)}, {DC_R, DC_RW}, pr));
+    }
+    for (int64_t i = k + 1; i < T; ++i) {
+      const dc_handle xi = bf ? s(i, k) : w(i, k);
+      TRY(submit(rt, DC_SYRK, {xi, D[i]}, {DC_R, DC_RW}, i == k + 1 ? 0 : 2));
+      for (int64_t j = k + 1; j < i; ++j) {
+        const dc_handle xj = bf ? s(j, k) : w(j, k);
+        TRY(submit(rt, DC_GEMM, {xi, xj, w(i, j)}, {DC_R, DC_R, DC_RW}, j == k + 1 ? 1 : 2));
+      }
+    }
+  }
+  return 0;
+}
+
+}  // namespace
+
+extern "C" int dc_posv_ir(dc_runtime *rt, dc_handle A, dc_handle B, dc_handle X, int64_t tile,
+                          dc_dtype upd, double tol, int maxit, dc_ir_report *rep) {
+  if (!rt) return -EINVAL;
+  if (rt->cfg.device < 0) return -ENODEV;
+  Handle *pa = rt->get(A), *pb = rt->get(B), *px = rt->get(X);
+  if (!pa || !pb || !px) return -ENOENT;
+  const int64_t n = pa->rows, r = pb->cols;
+  if (pa->cols != n || pa->dtype != DC_F64 || pb->dtype != DC_F64 || px->dtype != DC_F64 ||
+      pb->rows != n || px->rows != n || px->cols != r || tile < 1 || tile > dcx::MAX_TILE ||
+      !(tol > 0) || maxit < 0 || (upd != DC_F64 && upd != DC_F32 && upd != DC_BF16))
+    return -EINVAL;
+  if (pa->partitioned || pb->partitioned || px->partitioned) return -EBUSY;
+  dc_ir_report local;
+  memset(&local, 0, sizeof(local));
+  if (!rep) rep = &local;
+  memset(rep, 0, sizeof(*rep));
+  if (n == 0 || r == 0) { rep->converged = 1; return 0; }
+  TRY(dc_wait_all(rt));
+
+  const int64_t T = (n + tile - 1) / tile;
+  // workspace: diagonal tiles | off-diagonal FP32 or FP64 | BF16 copies | R
+  auto al = [](size_t v) { return (v + 255) / 256 * 256; };
+  Scratch ws;
+  std::vector<double> hx((size_t)n * r), hd((size_t)n * r);
+
+  dc_dtype prec = upd;
+  for (;;) {
+    const size_t es = prec == DC_F64 ? 8 : 4;
+    const size_t o_d = 0;
+    const size_t o_w = al(o_d + (size_t)T * tile * tile * 8);
+    const size_t o_s = al(o_w + (size_t)n * n * es);
+    const size_t o_r = al(o_s + (prec == DC_BF16 ? (size_t)n * n * 2 : 0));
+    const size_t total = al(o_r + (size_t)n * r * 8);
+    TRY(ws.get(total));
+    char *base = (char *)ws.ptr;
+    Regs regs(rt);
+    dc_handle hW, hS = 0, hR;
+    TRY(regs.mat(&hW, base + o_w, n, n, n, prec == DC_F64 ? DC_F64 : DC_F32, A));
+    if (prec == DC_BF16) TRY(regs.mat(&hS, base + o_s, n, n, n, DC_BF16, A));
+    TRY(regs.mat(&hR, base + o_r, n, r, r, DC_F64, 0));
+    std::vector<dc_handle> D(T);
+    for (int64_t k = 0; k < T; ++k) {
+      const int64_t nb = std::min(tile, n - k * tile);
+      TRY(regs.mat(&D[k], base + o_d + (size_t)k * tile * tile * 8, nb, nb, tile, DC_F64, A));
+    }
+
+    // ---- factor
+    double t0 = now_ms();
+    int64_t info = 0;
+    {
+      std::vector<dc_handle> At(T * T), W(T * T), S(T * T, 0);
+      TRY(dc_matrix_partition(rt, A, tile, At.data()));
+      int e = dc_matrix_partition(rt, hW, tile, W.data());
+      if (!e && hS) e = dc_matrix_partition(rt, hS, tile, S.data());
+      if (!e) e = submit_mixed_factor(rt, T, tile, At, D, W, S, prec);
+      if (!e) e = dc_wait_all(rt);
+      if (hS) dc_matrix_unpartition(rt, hS);
+      dc_matrix_unpartition(rt, hW);
+      dc_matrix_unpartition(rt, A);
+      TRY(e);
+      TRY(dc_get_info(rt, A, &info));
+    }
+    rep->factor_ms = now_ms() - t0;
+    if (info != 0) {
+      if (prec == DC_F64) { rep->final_prec = DC_F64; return 0; }   // A not SPD: info set
+      prec = prec == DC_BF16 ? DC_F32 : DC_F64;
+      rep->fallbacks++;
+      continue;
+    }
+
+    // ---- solve and refine
+    double t1 = now_ms();
+    std::vector<dc_handle> Wt(T * T), L(T * T), Xb, Rb;
+    TRY(dc_matrix_partition(rt, hW, tile, Wt.data()));
+    for (int64_t i = 0; i < T; ++i)
+      for (int64_t j = 0; j < T; ++j) L[i * T + j] = i == j ? D[i] : Wt[i * T + j];
+    auto solve_into = [&](dc_handle V) -> int {
+      // V (n x r) is solved in place with the mixed factor
+      std::vector<dc_handle> vt(T * ((r + tile - 1) / tile));
+      TRY(dc_matrix_partition(rt, V, tile, vt.data()));
+      const int64_t tc = (r + tile - 1) / tile;
+      std::vector<dc_handle> rows(T);
+      int e = 0;
+      for (int64_t j = 0; j < tc && !e; ++j) {
+        for (int64_t i = 0; i < T; ++i) rows[i] = vt[i * tc + j];
+        e = dcx_submit_potrs_tiles(rt, L, T, rows);
+      }
+      if (!e) e = dc_wait_all(rt);
+      dc_matrix_unpartition(rt, V);
+      return e;
+    };
+    int e = submit(rt, DC_CAST, {B, X}, {DC_R, DC_W}, 0);
+    if (!e) e = dc_wait_all(rt);
+    if (!e) e = solve_into(X);
+    std::vector<double> prev(r, INFINITY);
+    int it = 0;
+    bool converged = false, stagnated = false;
+    double last = 0.0;
+    while (!e) {
+      e = submit(rt, DC_RESID, {A, X, B, hR}, {DC_R, DC_R, DC_R, DC_W}, 0);
+      if (!e) e = dc_wait_all(rt);
+      if (!e) e = solve_into(hR);
+      if (e) break;
+      if (hipMemcpy(hd.data(), base + o_r, hd.size() * 8, hipMemcpyDeviceToHost) != hipSuccess ||
+          hipMemcpy2D(hx.data(), r * 8, px->ptr, px->ld * 8, r * 8, n, hipMemcpyDeviceToHost) !=
+              hipSuccess) {
+        e = -EIO;
+        break;
+      }
+      bool all_small = true, any_grow = false;
+      last = 0.0;
+      std::vector<double> dn(r, 0.0), xn(r, 0.0);
+      for (int64_t i = 0; i < n; ++i)
+        for (int64_t c = 0; c < r; ++c) {
+          dn[c] = std::max(dn[c], std::fabs(hd[i * r + c]));
+          xn[c] = std::max(xn[c], std::fabs(hx[i * r + c]));
+        }
+      for (int64_t c = 0; c < r; ++c) {
+        if (!(dn[c] <= tol * xn[c])) all_small = false;
+        if (it > 0 && dn[c] > 0.5 * prev[c]) any_grow = true;
+        last = std::max(last, xn[c] > 0 ? dn[c] / xn[c] : dn[c]);
+      }
+      if (any_grow && !all_small) { stagnated = true; break; }
+      e = submit(rt, DC_AXPY, {hR, X}, {DC_R, DC_RW}, 0);
+      if (!e) e = dc_wait_all(rt);
+      if (e) break;
+      if (all_small) { converged = true; break; }
+      prev = dn;
+      if (++it >= maxit) break;
+    }
+    dc_matrix_unpartition(rt, hW);
+    TRY(e);
+    rep->refine_ms = now_ms() - t1;
+    rep->iterations = it;
+    rep->converged = converged ? 1 : 0;
+    rep->last_update = last;
+    rep->final_prec = prec;
+    if (converged || prec == DC_F64) return 0;
+    (void)stagnated;
+    prec = prec == DC_BF16 ? DC_F32 : DC_F64;
+    rep->fallbacks++;
+  }
+}

@@ -56,6 +56,30 @@ dc_handle dc_runtime::root_of(dc_handle h) {
   }
 }
 
+dc_handle dc_runtime::new_handle(const Handle &h) {
+  if (!free_ids.empty()) {
+    const dc_handle id = free_ids.back();
+    free_ids.pop_back();
+    handles[id - 1] = h;
+    return id;
+  }
+  handles.push_back(h);
+  return (dc_handle)handles.size();
+}
+
+void dc_runtime::free_handle(dc_handle h) {
+  Handle *p = get(h);
+  if (!p) return;
+  *p = Handle();
+  free_ids.push_back(h);
+}
+
+dc_handle dc_runtime::status_root_of(dc_handle h) {
+  const dc_handle r = root_of(h);
+  const dc_handle s = handles[r - 1].status_root;
+  return s ? s : r;
+}
+
 void dc_runtime::reset_graph_state() {
   for (dc_handle h : touched) {
     Handle *p = &handles[h - 1];
@@ -106,7 +130,10 @@ extern "C" int dc_init(dc_runtime **out, const dc_config *cfg) {
     int cus = 0;
     hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c.device);
     he = (hipError_t)dcx_level_setup();
+    if (he == hipSuccess) he = (hipError_t)dcx_gemm_setup();
     if (he != hipSuccess) { delete rt; return fail_hip(he, "hipFuncSetAttribute"); }
+    he = hipStreamCreateWithFlags(&rt->side, hipStreamNonBlocking);
+    if (he != hipSuccess) { delete rt; return fail_hip(he, "hipStreamCreate(side)"); }
     rt->num_cus = std::max(1, cus);
     rt->default_workers = rt->num_cus;
     int rate_khz = 0;
@@ -131,6 +158,8 @@ extern "C" int dc_shutdown(dc_runtime *rt) {
   if (rt->cfg.device >= 0) {
     err = dc_wait_all(rt);
     free_device(rt);
+    for (hipEvent_t e : rt->events) hipEventDestroy(e);
+    if (rt->side) hipStreamDestroy(rt->side);
     if (rt->own_stream) hipStreamDestroy(rt->stream);
   }
   delete rt;
@@ -152,8 +181,7 @@ static int register_common(dc_runtime *rt, dc_handle *out, void *ptr, int64_t ro
   h.ld = ld;
   h.dtype = dtype;
   h.alive = true;
-  rt->handles.push_back(h);
-  dc_handle id = (dc_handle)rt->handles.size();
+  const dc_handle id = rt->new_handle(h);
   rt->by_ptr[ptr] = id;
   *out = id;
   return 0;
@@ -215,8 +243,7 @@ extern "C" int dc_matrix_partition(dc_runtime *rt, dc_handle m, int64_t tile,
       h.tj = J;
       h.row_off = parent.row_off + I * tile;
       h.alive = true;
-      rt->handles.push_back(h);
-      ids.push_back((dc_handle)rt->handles.size());
+      ids.push_back(rt->new_handle(h));
     }
   p = rt->get(m);
   p->partitioned = true;
@@ -233,9 +260,9 @@ static void drop_tiles(dc_runtime *rt, dc_handle m) {
   if (!p) return;
   for (dc_handle t : p->tiles) {
     drop_tiles(rt, t);
-    Handle *c = rt->get(t);
-    if (c) c->alive = false;
+    rt->free_handle(t);
   }
+  p = rt->get(m);
   p->tiles.clear();
   p->partitioned = false;
 }
@@ -275,7 +302,7 @@ extern "C" int dc_unregister(dc_runtime *rt, dc_handle h) {
   drop_tiles(rt, h);
   p = rt->get(h);
   rt->by_ptr.erase(p->ptr);
-  p->alive = false;
+  rt->free_handle(h);
   return 0;
 }
 
@@ -296,7 +323,7 @@ extern "C" int dc_get_info(dc_runtime *rt, dc_handle m, int64_t *info) {
   if (!rt || !info) return -EINVAL;
   Handle *p = rt->get(m);
   if (!p) return -ENOENT;
-  *info = rt->handles[rt->root_of(m) - 1].info;
+  *info = rt->handles[rt->status_root_of(m) - 1].info;
   return 0;
 }
 
@@ -320,6 +347,7 @@ static const KindSig kSig[DC_NUM_KINDS] = {
     {2, {DC_R, DC_W}},                  // CAST
     {4, {DC_R, DC_R, DC_R, DC_W}},      // RESID
     {2, {DC_R, DC_RW}},                 // AXPY
+    {3, {DC_R, DC_RW, DC_W}},           // TRSM_CAST
 };
 
 static int units_for(const TaskDesc &d) {
@@ -327,7 +355,7 @@ static int units_for(const TaskDesc &d) {
   switch (d.kind) {
     case K_GEMM: return std::max(1, cdiv(d.m, GEMM_UNIT) * cdiv(d.n, GEMM_UNIT));
     case K_SYRK: { int p = cdiv(d.m, GEMM_UNIT); return std::max(1, p * (p + 1) / 2); }
-    case K_TRSM: return std::max(1, cdiv(d.m, trsm_rows(d.n)));
+    case K_TRSM: case K_TRSM_CAST: return std::max(1, cdiv(d.m, trsm_rows(d.n)));
     case K_GEMM_RHS_N: case K_GEMM_RHS_T: case K_CAST: case K_RESID: case K_AXPY:
       return std::max(1, cdiv(d.m, ROW_UNIT));
     case K_SCAL: return std::max(1, cdiv(d.m, 4096));
@@ -356,18 +384,26 @@ static int make_desc(dc_runtime *rt, dc_kind kind, const std::vector<Handle *> &
       d.row0 = row0;
       break;
     }
-    case DC_TRSM: {
+    case DC_TRSM: case DC_TRSM_CAST: {
       Handle *L = H[0], *X = H[1];
-      if (!f64(L) || !f64(X)) return -EINVAL;
+      if (!f64(L) || (X->dtype != DC_F64 && X->dtype != DC_F32)) return -EINVAL;
       if (L->rows != L->cols || X->cols != L->rows || L->rows > MAX_TILE) return -EINVAL;
       d.m = (int)X->rows; d.n = (int)L->rows;
       d.a = L->ptr; d.lda = L->ld; d.ta = L->dtype;
       d.c = X->ptr; d.ldc = X->ld; d.tc = X->dtype;
+      if (kind == DC_TRSM_CAST) {
+        Handle *S = H[2];
+        if (X->dtype != DC_F32 || S->dtype != DC_BF16 || S->rows != X->rows || S->cols != X->cols)
+          return -EINVAL;
+        d.d = S->ptr; d.ldd = S->ld;
+      }
       break;
     }
     case DC_SYRK: {
       Handle *X = H[0], *C = H[1];
-      if (!f64(X) || !f64(C)) return -EINVAL;
+      // FP64 inputs update an FP64 tile; FP32/BF16 inputs (FP32 accumulation)
+      // update an FP64 or FP32 tile
+      if (f64(X) ? !f64(C) : (C->dtype == DC_BF16)) return -EINVAL;
       if (C->rows != C->cols || X->rows != C->rows) return -EINVAL;
       d.m = (int)C->rows; d.k = (int)X->cols;
       d.a = X->ptr; d.lda = X->ld; d.ta = X->dtype;
@@ -376,7 +412,7 @@ static int make_desc(dc_runtime *rt, dc_kind kind, const std::vector<Handle *> &
     }
     case DC_GEMM: {
       Handle *X = H[0], *Y = H[1], *C = H[2];
-      if (!f64(X) || !f64(Y) || !f64(C)) return -EINVAL;
+      if (X->dtype != Y->dtype || (f64(X) ? !f64(C) : (C->dtype == DC_BF16))) return -EINVAL;
       if (X->rows != C->rows || Y->rows != C->cols || X->cols != Y->cols) return -EINVAL;
       d.m = (int)C->rows; d.n = (int)C->cols; d.k = (int)X->cols;
       d.a = X->ptr; d.lda = X->ld; d.ta = X->dtype;
@@ -478,9 +514,8 @@ extern "C" int dc_task_submit(dc_runtime *rt, dc_kind kind, int nbuf, const dc_h
   if (rt->tasks.size() >= (size_t)INT32_MAX / 2) return -ENOMEM;
 
   // numerical-status slot: the root matrix of the factor this task touches
-  if (kind <= DC_GEMM_RHS_T) {
-    dc_handle root = rt->root_of(bufs[0]);
-    if (kind == DC_POTRF) root = rt->root_of(bufs[0]);
+  if (kind <= DC_GEMM_RHS_T || kind == DC_TRSM_CAST) {
+    const dc_handle root = rt->status_root_of(bufs[0]);
     auto it = rt->slot_of.find(root);
     int slot;
     if (it == rt->slot_of.end()) {
@@ -616,8 +651,7 @@ static int finalize(dc_runtime *rt) {
 // LDS bytes the level kernel needs for a unit of this task.
 static size_t lds_for(const TaskDesc &d) {
   switch (d.kind) {
-    case K_GEMM: case K_SYRK: return (size_t)GEMM_LDS_DOUBLES * 8;
-    case K_TRSM: return (size_t)trsm_lds_doubles(d.n) * 8;
+    case K_TRSM: case K_TRSM_CAST: return (size_t)trsm_lds_doubles(d.n) * 8;
     case K_POTRF: return (size_t)potrf_lds_doubles(d.m) * 8;
     case K_TRSM_L: case K_TRSM_LT: return (size_t)(16 * 16 * 16 + 16 * 16) * 8;
     case K_GEMM_RHS_T: return (size_t)(4 * 64 * 8) * 8;
@@ -630,10 +664,10 @@ static size_t lds_for(const TaskDesc &d) {
 static double cost_ns(const TaskDesc &d) {
   const double m = d.m, n = d.n, k = d.k;
   switch (d.kind) {
-    case K_GEMM: return 2.0 * m * n * k / 250.0;
-    case K_SYRK: return m * m * k / 250.0;
-    case K_TRSM: return m * n * n / 120.0;
-    case K_POTRF: return m * m * m / 3.0 / 40.0 + 2000.0;
+    case K_GEMM: return 2.0 * m * n * k / (d.ta == T_F64 ? 200.0 : 400.0);
+    case K_SYRK: return m * m * k / (d.ta == T_F64 ? 200.0 : 400.0);
+    case K_TRSM: case K_TRSM_CAST: return m * n * n / 60.0;
+    case K_POTRF: return m * m * m / 3.0 / 30.0 + 2000.0;
     case K_TRSM_L: case K_TRSM_LT: return m * m * 8.0 / 20.0 + 2000.0;
     case K_GEMM_RHS_N: case K_GEMM_RHS_T: return m * k * 8.0 / 50.0;
     case K_RESID: return m * m * 8.0 / 50.0;
@@ -706,11 +740,15 @@ extern "C" int dc_flush(dc_runtime *rt) {
   const int workers_cfg = rt->cfg.workers > 0 ? rt->cfg.workers : rt->num_cus;
   std::vector<int32_t> level;
   const int64_t nl = assign_levels(rt, workers_cfg, level);
+  // per level: panel-kernel units first, then GEMM/SYRK units
+  auto is_gemm = [](const TaskDesc &d) { return d.kind == K_GEMM || d.kind == K_SYRK; };
   int64_t total_units = 0;
-  std::vector<int64_t> lcount(nl, 0);
+  std::vector<int64_t> pcount(nl, 0), gcount(nl, 0), lcount(nl, 0);
   for (int64_t t = 0; t < nt; ++t) {
-    total_units += rt->tasks[t].desc.nunits;
-    lcount[level[t]] += rt->tasks[t].desc.nunits;
+    const TaskDesc &d = rt->tasks[t].desc;
+    total_units += d.nunits;
+    (is_gemm(d) ? gcount : pcount)[level[t]] += d.nunits;
+    lcount[level[t]] += d.nunits;
   }
   if (total_units >= INT32_MAX) { drop(); return -ENOMEM; }
   const int nslots_roots = (int)rt->slot_roots.size();
@@ -720,7 +758,7 @@ extern "C" int dc_flush(dc_runtime *rt) {
   auto take = [&](int64_t bytes) { int64_t o = off; off = align_up(off + bytes, 256); return o; };
   const int64_t o_desc = take(nt * (int64_t)sizeof(TaskDesc));
   const int64_t o_items = take(total_units * 8);
-  const int64_t o_cnt = take(nl * 8);
+  const int64_t o_cnt = take(2 * nl * 8);
   const int64_t o_tail = off;
   const int64_t o_info = take(std::max(nslots_roots, 1) * 8);
   const int64_t o_failed = take(std::max(nslots_roots, 1) * 4);
@@ -746,6 +784,8 @@ extern "C" int dc_flush(dc_runtime *rt) {
   uint64_t *items = (uint64_t *)(hb + o_items);
   std::vector<int64_t> lbegin(nl, 0);
   for (int64_t L = 1; L < nl; ++L) lbegin[L] = lbegin[L - 1] + lcount[L - 1];
+  std::vector<int64_t> gbegin(nl, 0);
+  for (int64_t L = 0; L < nl; ++L) gbegin[L] = lbegin[L] + pcount[L];
   // order inside a level: urgent priority lanes first, then longer units
   std::vector<int64_t> order(nt);
   for (int64_t t = 0; t < nt; ++t) order[t] = t;
@@ -756,18 +796,20 @@ extern "C" int dc_flush(dc_runtime *rt) {
     const double cy = cost_ns(rt->tasks[y].desc) / rt->tasks[y].desc.nunits;
     return cx > cy;
   });
-  std::vector<int64_t> fillp(lbegin);
+  std::vector<int64_t> fillp(lbegin), fillg(gbegin);
   std::vector<size_t> llds(nl, 16);
   for (int64_t i = 0; i < nt; ++i) {
     const int64_t t = order[i];
     const Task &k = rt->tasks[t];
     desc[t] = k.desc;
     const int L = level[t];
-    llds[L] = std::max(llds[L], lds_for(k.desc));
+    const bool g = is_gemm(k.desc);
+    if (!g) llds[L] = std::max(llds[L], lds_for(k.desc));
+    int64_t &fp = g ? fillg[L] : fillp[L];
     for (int u = 0; u < k.desc.nunits; ++u)
-      items[fillp[L]++] = ((uint64_t)(uint32_t)t << 32) | (uint32_t)u;
+      items[fp++] = ((uint64_t)(uint32_t)t << 32) | (uint32_t)u;
   }
-  memset(hb + o_cnt, 0, nl * 8);
+  memset(hb + o_cnt, 0, 2 * nl * 8);
   memset(hb + o_info, 0, std::max(nslots_roots, 1) * 8);
   memset(hb + o_failed, 0, std::max(nslots_roots, 1) * 4);
   if (trace) {
@@ -782,28 +824,57 @@ extern "C" int dc_flush(dc_runtime *rt) {
   if (e != hipSuccess) { drop(); return fail_hip(e, "hipMemcpyAsync(graph)"); }
   char *db = (char *)rt->arena_dev;
   int max_workers = 0;
+  size_t nevents = 0;
   for (int64_t L = 0; L < nl; ++L) {
     LevelArgs a;
     a.desc = (const TaskDesc *)(db + o_desc);
     a.items = (const uint64_t *)(db + o_items);
-    a.begin = lbegin[L];
-    a.count = lcount[L];
-    a.counter = (unsigned long long *)(db + o_cnt) + L;
     a.failed = (int32_t *)(db + o_failed);
     a.info = (int64_t *)(db + o_info);
     a.trace = trace ? (int64_t *)(db + o_trace) : nullptr;
-    int per_cu = 1;
-    dcx_level_occupancy(llds[L], &per_cu);
-    int workers = rt->cfg.workers > 0 ? rt->cfg.workers : rt->num_cus * std::max(1, per_cu);
-    workers = (int)std::min<int64_t>(workers, lcount[L]);
-    if (workers <= 0) continue;
-    max_workers = std::max(max_workers, workers);
-    int le = dcx_launch_level(a, workers, llds[L], rt->stream);
-    if (le != 0) {
-      fail_hip((hipError_t)le, "level launch");
-      drop();
-      return -EIO;
+    const bool hasp = pcount[L] > 0, hasg = gcount[L] > 0;
+    const int cus = rt->cfg.workers > 0 ? rt->cfg.workers : rt->num_cus;
+    int pworkers = 0;
+    if (hasp) {
+      int per_cu = 1;
+      dcx_level_occupancy(llds[L], &per_cu);
+      pworkers = (int)std::min<int64_t>(pcount[L], (int64_t)cus * std::max(1, per_cu));
+      if (hasg) pworkers = std::min(pworkers, std::max(1, cus / 2));
     }
+    int gworkers = hasg ? (int)std::min<int64_t>(gcount[L], std::max(1, cus - pworkers)) : 0;
+    hipStream_t pstream = rt->stream;
+    if (hasp && hasg) {
+      // fork: the panel units run on the side stream next to the GEMM units
+      while (rt->events.size() < nevents + 2) {
+        hipEvent_t ev;
+        if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) { drop(); return -EIO; }
+        rt->events.push_back(ev);
+      }
+      hipEventRecord(rt->events[nevents], rt->stream);
+      hipStreamWaitEvent(rt->side, rt->events[nevents], 0);
+      pstream = rt->side;
+    }
+    if (hasp) {
+      a.begin = lbegin[L];
+      a.count = pcount[L];
+      a.counter = (unsigned long long *)(db + o_cnt) + 2 * L;
+      int le = dcx_launch_level(a, pworkers, llds[L], pstream);
+      if (le != 0) { fail_hip((hipError_t)le, "level launch"); drop(); return -EIO; }
+    }
+    if (hasg) {
+      a.begin = gbegin[L];
+      a.count = gcount[L];
+      a.counter = (unsigned long long *)(db + o_cnt) + 2 * L + 1;
+      int le = dcx_launch_gemm(a, gworkers, rt->stream);
+      if (le != 0) { fail_hip((hipError_t)le, "gemm launch"); drop(); return -EIO; }
+    }
+    if (hasp && hasg) {
+      // join
+      hipEventRecord(rt->events[nevents + 1], rt->side);
+      hipStreamWaitEvent(rt->stream, rt->events[nevents + 1], 0);
+      nevents += 2;
+    }
+    max_workers = std::max(max_workers, pworkers + gworkers);
   }
   Inflight &f = rt->fl;
   f.tail_off = o_tail;

@@ -30,6 +30,9 @@ struct Handle {
   int pending = 0;
   // numerical status of the last factorisation (top-level handles)
   int64_t info = 0;
+  // top-level handle whose numerical status this handle's tasks share (0:
+  // its own); workspace tiles of a factorisation report into the matrix
+  dc_handle status_root = 0;
 };
 
 struct Task {
@@ -50,12 +53,15 @@ struct Inflight {
 struct dc_runtime {
   dc_config cfg{};
   hipStream_t stream = nullptr;
+  hipStream_t side = nullptr;                  // panel units next to GEMM units
+  std::vector<hipEvent_t> events;              // fork/join events, reused per flush
   bool own_stream = false;
   int num_cus = 0;
   int default_workers = 1;
   int wall_clock_khz = 100000;
 
   std::vector<Handle> handles;                 // id - 1 -> handle
+  std::vector<dc_handle> free_ids;             // slots of unregistered handles
   std::unordered_map<void *, dc_handle> by_ptr;
   std::vector<dc_handle> touched;              // handles referenced by pending tasks
   std::vector<Task> tasks;                     // pending graph
@@ -81,5 +87,8 @@ struct dc_runtime {
 
   Handle *get(dc_handle h);
   dc_handle root_of(dc_handle h);
+  dc_handle status_root_of(dc_handle h);
+  dc_handle new_handle(const Handle &h);
+  void free_handle(dc_handle h);
   void reset_graph_state();
 };

@@ -27,7 +27,7 @@ dc_handle = ctypes.c_int64
 DC_R, DC_W, DC_RW = 1, 2, 3
 DC_F64, DC_F32, DC_BF16 = 0, 1, 2
 (DC_POTRF, DC_TRSM, DC_SYRK, DC_GEMM, DC_TRSM_L, DC_GEMM_RHS_N, DC_TRSM_LT, DC_GEMM_RHS_T,
- DC_SCAL, DC_CAST, DC_RESID, DC_AXPY) = range(12)
+ DC_SCAL, DC_CAST, DC_RESID, DC_AXPY, DC_TRSM_CAST) = range(13)
 
 ERRNO = {22: "EINVAL", 2: "ENOENT", 16: "EBUSY", 12: "ENOMEM", 19: "ENODEV", 110: "ETIMEDOUT",
          5: "EIO", 38: "ENOSYS"}
@@ -49,6 +49,25 @@ class dc_ir_report(ctypes.Structure):
                 ("final_prec", ctypes.c_int), ("fallbacks", ctypes.c_int),
                 ("last_update", ctypes.c_double), ("factor_ms", ctypes.c_double),
                 ("refine_ms", ctypes.c_double)]
+
+
+class dc_server_config(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int), ("slots", ctypes.c_int), ("pool_bytes", ctypes.c_size_t),
+                ("tile", ctypes.c_int64), ("upd", ctypes.c_int), ("tol", ctypes.c_double),
+                ("maxit", ctypes.c_int)]
+
+
+class dc_request(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("r", ctypes.c_int64), ("A", ctypes.c_void_p),
+                ("B", ctypes.c_void_p), ("X", ctypes.c_void_p), ("arrival", ctypes.c_double)]
+
+
+class dc_request_result(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_int64), ("status", ctypes.c_int), ("info", ctypes.c_int64),
+                ("converged", ctypes.c_int), ("iterations", ctypes.c_int),
+                ("final_prec", ctypes.c_int), ("restarts", ctypes.c_int),
+                ("last_update", ctypes.c_double), ("arrival", ctypes.c_double),
+                ("admitted", ctypes.c_double), ("completed", ctypes.c_double)]
 
 
 _P = ctypes.c_void_p
@@ -88,6 +107,15 @@ _SIGS = {
     "dc_posv_ir": (ctypes.c_int, [_P, _H, _H, _H, _I64, ctypes.c_int, ctypes.c_double,
                                   ctypes.c_int, ctypes.POINTER(dc_ir_report)]),
     "dc_last_launch": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double), _PI64, _PI32]),
+    "dc_potrf_batched": (ctypes.c_int, [_P, _I64, _PH, _PH, _PI64, _PI64]),
+    "dc_server_config_default": (None, [ctypes.POINTER(dc_server_config)]),
+    "dc_server_create": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.POINTER(dc_server_config)]),
+    "dc_server_destroy": (ctypes.c_int, [_P]),
+    "dc_server_now": (ctypes.c_double, [_P]),
+    "dc_server_submit": (ctypes.c_int, [_P, ctypes.POINTER(dc_request), _PI64]),
+    "dc_server_progress": (ctypes.c_int, [_P, ctypes.POINTER(dc_request_result), ctypes.c_int,
+                                          ctypes.POINTER(ctypes.c_int),
+                                          ctypes.POINTER(ctypes.c_int)]),
 }
 
 for _name, (_res, _args) in _SIGS.items():
@@ -273,6 +301,16 @@ class Runtime:
     def dc_potrs(self, l, b, tile):
         _check(_lib.dc_potrs(self._ptr, l, b, tile), "dc_potrs")
 
+    def dc_potrf_batched(self, a_handles, b_handles, tiles):
+        n = len(a_handles)
+        ha = (dc_handle * max(n, 1))(*a_handles)
+        hb = (dc_handle * max(n, 1))(*(b_handles or [0] * n))
+        tl = (ctypes.c_int64 * max(n, 1))(*tiles)
+        info = (ctypes.c_int64 * max(n, 1))()
+        _check(_lib.dc_potrf_batched(self._ptr, n, ha, hb if b_handles is not None else None,
+                                     tl, info), "dc_potrf_batched")
+        return [info[i] for i in range(n)]
+
     def dc_posv_ir(self, a, b, x, tile, upd=DC_F32, tol=1e-12, maxit=30):
         rep = dc_ir_report()
         _check(_lib.dc_posv_ir(self._ptr, a, b, x, tile, upd, tol, maxit, ctypes.byref(rep)),
@@ -336,3 +374,90 @@ def posv_ir(rt, a, b, x, tile, upd=DC_F32, tol=1e-12, maxit=30):
     finally:
         for h in (hx, hb, ha):
             rt.dc_unregister(h)
+
+
+def potrf_batched(rt, mats, rhs=None, tiles=None):
+    """Factors every CUDA float64 matrix of ``mats`` in place (and solves the
+    matching ``rhs`` in place) in one graph; returns the per-matrix infos."""
+    ha = [rt.register_tensor(m) for m in mats]
+    hb = [rt.register_tensor(b) for b in rhs] if rhs is not None else None
+    try:
+        return rt.dc_potrf_batched(ha, hb, tiles if tiles is not None else [0] * len(mats))
+    finally:
+        for h in (hb or []) + ha:
+            rt.dc_unregister(h)
+
+
+# ------------------------------------------------------------------ serving
+
+class Server:
+    """Continuous-batching solve server (dc_server_*).  Tensors handed to
+    submit() are kept alive here until their request completes."""
+
+    def __init__(self, device=0, slots=4, pool_bytes=None, tile=256, upd=DC_F32, tol=1e-12,
+                 maxit=30):
+        cfg = dc_server_config()
+        _lib.dc_server_config_default(ctypes.byref(cfg))
+        cfg.device, cfg.slots, cfg.tile, cfg.upd = device, slots, tile, upd
+        cfg.tol, cfg.maxit = tol, maxit
+        if pool_bytes is not None:
+            cfg.pool_bytes = pool_bytes
+        p = _P()
+        _check(_lib.dc_server_create(ctypes.byref(p), ctypes.byref(cfg)), "dc_server_create")
+        self._ptr = p
+        self._keep = {}
+        self._res = (dc_request_result * 256)()
+
+    def now(self):
+        return _lib.dc_server_now(self._ptr)
+
+    def submit(self, a, b, x, arrival=None):
+        """A (n x n), B and X (n x r): contiguous CUDA float64 tensors."""
+        for t in (a, b, x):
+            if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous():
+                raise ValueError("server tensors must be contiguous CUDA float64")
+        b2 = b if b.dim() == 2 else b.view(-1, 1)
+        x2 = x if x.dim() == 2 else x.view(-1, 1)
+        q = dc_request(n=a.shape[0], r=b2.shape[1], A=a.data_ptr(), B=b2.data_ptr(),
+                       X=x2.data_ptr(), arrival=self.now() if arrival is None else arrival)
+        rid = ctypes.c_int64()
+        _check(_lib.dc_server_submit(self._ptr, ctypes.byref(q), ctypes.byref(rid)),
+               "dc_server_submit")
+        self._keep[rid.value] = (a, b, x)
+        return rid.value
+
+    def progress(self):
+        """Returns (completed results as dicts, number still queued or running)."""
+        nd, act = ctypes.c_int(), ctypes.c_int()
+        _check(_lib.dc_server_progress(self._ptr, self._res, len(self._res), ctypes.byref(nd),
+                                       ctypes.byref(act)), "dc_server_progress")
+        out = []
+        for i in range(nd.value):
+            r = self._res[i]
+            d = {f: getattr(r, f) for f, _ in dc_request_result._fields_}
+            self._keep.pop(d["id"], None)
+            out.append(d)
+        return out, act.value
+
+    def drain(self, sleep=0.0):
+        import time
+        done = []
+        while True:
+            got, act = self.progress()
+            done += got
+            if act == 0:
+                return done
+            if sleep:
+                time.sleep(sleep)
+
+    def close(self):
+        if self._ptr:
+            _check(_lib.dc_server_destroy(self._ptr), "dc_server_destroy")
+            self._ptr = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -167,7 +167,7 @@ def test_ragged_partition_shapes(dc):
         with pytest.raises(dc.DagcholError):
             rt.dc_task_submit(dc.DC_TRSM, [tiles[2][2], tiles[2][0]], [dc.DC_R, dc.DC_RW])
         st = rt.dc_graph_stats_get()
-        assert st["ntasks"] == 1 and st["nunits"] == -(-232 // 32)
+        assert st["ntasks"] == 1 and st["nunits"] == -(-232 // 16)
 
 
 def test_strerror(dc):

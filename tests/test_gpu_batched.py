@@ -1,0 +1,108 @@
+"""GPU parity of the batched path: many independent factorisations and
+solves in one graph.
+
+Each matrix is checked against the oracle (backward error <= 1e-13 and the
+solution within 16 n u cond(A) of the oracle's); a matrix gives bit-identical
+results alone and inside the batch; a non-SPD matrix in the batch reports its
+own breakdown column and leaves the others bit-identical.
+"""
+import numpy as np
+import pytest
+
+from oracle import core
+from paper_1304_0878_amd import inputs
+
+pytestmark = pytest.mark.gpu
+U = 2.0 ** -53
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch, torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def dc():
+    from paper_1304_0878_amd import dagchol
+    return dagchol
+
+
+@pytest.fixture()
+def rt(dc, torch_dev):
+    r = dc.Runtime(device=0)
+    yield r
+    r.close()
+
+
+def _batch(count, seed, nmax=300):
+    ns, rs = inputs.batch_shapes(count, seed, nmin=16, nmax=nmax)
+    mats = [inputs.spd_uniform(n, seed * 100000 + i) for i, n in enumerate(ns)]
+    rhs = [inputs.rhs(n, r, seed * 100000 + 50000 + i) for i, (n, r) in enumerate(zip(ns, rs))]
+    return ns, mats, rhs
+
+
+def _tile_rule(n):
+    return 0 if n <= 128 else 128
+
+
+def _run(dc, rt, torch_dev, mats, rhs, tiles):
+    torch, dev = torch_dev
+    ta = [torch.from_numpy(m).to(dev) for m in mats]
+    tb = [torch.from_numpy(b).to(dev) for b in rhs]
+    infos = dc.potrf_batched(rt, ta, tb, tiles)
+    return infos, [np.tril(t.cpu().numpy()) for t in ta], [t.cpu().numpy() for t in tb]
+
+
+def test_batched_matches_oracle(dc, rt, torch_dev):
+    ns, mats, rhs = _batch(120, 1)
+    tiles = [_tile_rule(n) for n in ns]
+    infos, ls, xs = _run(dc, rt, torch_dev, mats, rhs, tiles)
+    assert infos == [0] * len(ns)
+    for a, b, l, x, t in zip(mats, rhs, ls, xs, tiles):
+        n = a.shape[0]
+        assert core.backward_error_fro(a, l) <= 1e-13
+        lr = np.tril(core.potrf_tiled(a, t or n)[0])
+        xr = core.potrs_tiled(lr, b, t or n)
+        assert np.abs(x - xr).max() / np.abs(xr).max() <= 16 * n * U * np.linalg.cond(a)
+
+
+def test_batched_alone_equals_in_batch(dc, rt, torch_dev):
+    ns, mats, rhs = _batch(40, 2)
+    tiles = [_tile_rule(n) for n in ns]
+    _, ls, xs = _run(dc, rt, torch_dev, mats, rhs, tiles)
+    for i in (0, 7, 19, 39):
+        _, l1, x1 = _run(dc, rt, torch_dev, [mats[i]], [rhs[i]], [tiles[i]])
+        assert np.array_equal(l1[0], ls[i]) and np.array_equal(x1[0], xs[i])
+
+
+def test_batched_failure_is_isolated(dc, rt, torch_dev):
+    ns, mats, rhs = _batch(30, 3)
+    tiles = [_tile_rule(n) for n in ns]
+    _, ls, xs = _run(dc, rt, torch_dev, mats, rhs, tiles)
+    bad = [m.copy() for m in mats]
+    j = 11
+    k = ns[j] // 2
+    bad[j][k, k] = -1.0
+    infos, ls2, xs2 = _run(dc, rt, torch_dev, bad, rhs, tiles)
+    assert infos[j] == core.potrf_tiled(bad[j], tiles[j] or ns[j])[1] > 0
+    for i in range(len(ns)):
+        if i != j:
+            assert infos[i] == 0
+            assert np.array_equal(ls2[i], ls[i]) and np.array_equal(xs2[i], xs[i])
+
+
+def test_batched_integer_exact(dc, rt, torch_dev):
+    mats, rhs, sols = [], [], []
+    for i, n in enumerate((20, 64, 130, 257)):
+        a, l0 = inputs.integer_factor(n, 40 + i, diag_choices=(1.0, 2.0))
+        x0 = inputs.integer_solution(n, 2, 60 + i)
+        mats.append(a)
+        rhs.append(a @ x0)
+        sols.append((l0, x0))
+    infos, ls, xs = _run(dc, rt, torch_dev, mats, rhs, [0, 32, 64, 128])
+    assert infos == [0, 0, 0, 0]
+    for (l0, x0), l, x in zip(sols, ls, xs):
+        assert np.array_equal(l, l0) and np.array_equal(x, x0)

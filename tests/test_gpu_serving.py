@@ -1,0 +1,130 @@
+"""GPU tests of the continuous-batching solve server (dc_server_*).
+
+Bars:
+  * every served solution is within 1e-10 (relative, infinity norm) of the
+    oracle's FP64 solution refined with a long-double residual;
+  * a request's solution is bit-identical whether it was served alone or
+    among other requests (each request runs its own graph; concurrency only
+    changes when its units run, not what they compute);
+  * with a pool that holds one workspace at a time, requests are admitted
+    one after another and all complete;
+  * a non-SPD request reports its breakdown column, restarts once in FP64,
+    and leaves the other requests' results bit-identical;
+  * a request whose FP64 workspace can never fit is refused at submission.
+"""
+import numpy as np
+import pytest
+
+from oracle import mixed
+from paper_1304_0878_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch, torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def dc():
+    from paper_1304_0878_amd import dagchol
+    return dagchol
+
+
+def _systems(count, seed, nmin=100, nmax=900, kappa=1e4):
+    g = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        n = int(g.integers(nmin, nmax + 1))
+        r = int(g.integers(1, 4))
+        out.append((inputs.spd_cond(n, seed * 1000 + i, kappa), inputs.rhs(n, r, seed * 1000 + 500 + i)))
+    return out
+
+
+def _serve(dc, torch_dev, systems, **kw):
+    torch, dev = torch_dev
+    srv = dc.Server(device=0, **kw)
+    try:
+        xs, ids = [], []
+        for a, b in systems:
+            ta = torch.from_numpy(a).to(dev)
+            tb = torch.from_numpy(b).to(dev)
+            tx = torch.zeros_like(tb)
+            ids.append(srv.submit(ta, tb, tx))
+            xs.append(tx)
+        res = {d["id"]: d for d in srv.drain()}
+        torch.cuda.synchronize()
+        return [res[i] for i in ids], [x.cpu().numpy() for x in xs]
+    finally:
+        srv.close()
+
+
+@pytest.mark.parametrize("upd", ["f32", "bf16", "f64"])
+def test_server_solutions_match_oracle(dc, torch_dev, upd):
+    code = {"f32": dc.DC_F32, "bf16": dc.DC_BF16, "f64": dc.DC_F64}[upd]
+    systems = _systems(10, 3)
+    res, xs = _serve(dc, torch_dev, systems, slots=4, tile=128, upd=code)
+    for (a, b), r, x in zip(systems, res, xs):
+        assert r["status"] == 0 and r["converged"] == 1 and r["info"] == 0, r
+        assert r["final_prec"] == code and r["restarts"] == 0, r
+        assert r["arrival"] <= r["admitted"] <= r["completed"]
+        xref = mixed.reference_solution(a, b, 128)
+        assert np.abs(x - xref).max() / np.abs(xref).max() <= 1e-10, r
+
+
+def test_server_alone_equals_in_mix(dc, torch_dev):
+    systems = _systems(8, 4)
+    _, xs = _serve(dc, torch_dev, systems, slots=4, tile=128)
+    for i in (0, 5):
+        _, x1 = _serve(dc, torch_dev, [systems[i]], slots=1, tile=128)
+        assert np.array_equal(x1[0], xs[i])
+
+
+def test_server_small_pool_admits_one_at_a_time(dc, torch_dev):
+    systems = _systems(5, 5, nmin=500, nmax=500)
+    n = 500
+    tile = 128
+    t = (n + tile - 1) // tile
+    fp32 = t * tile * tile * 8 + n * n * 4 + n * 3 * 8 + 4 * 256
+    res, xs = _serve(dc, torch_dev, systems, slots=4, tile=tile, pool_bytes=int(fp32 * 1.5))
+    res = sorted(res, key=lambda r: r["admitted"])
+    for prev, cur in zip(res, res[1:]):
+        assert cur["admitted"] >= prev["completed"] - 1e-9
+    for (a, b), r, x in zip(systems, sorted(res, key=lambda r: r["id"]), xs):
+        assert r["converged"] == 1
+        xref = mixed.reference_solution(a, b, tile)
+        assert np.abs(x - xref).max() / np.abs(xref).max() <= 1e-10
+
+
+def test_server_non_spd_is_isolated(dc, torch_dev):
+    systems = _systems(6, 6)
+    res0, xs0 = _serve(dc, torch_dev, systems, slots=3, tile=128)
+    bad = list(systems)
+    a, b = systems[2]
+    a = a.copy()
+    k = a.shape[0] // 3
+    a[k, k] = -1.0
+    bad[2] = (a, b)
+    res, xs = _serve(dc, torch_dev, bad, slots=3, tile=128)
+    assert res[2]["info"] > 0 and res[2]["converged"] == 0
+    assert res[2]["final_prec"] == dc.DC_F64 and res[2]["restarts"] == 1
+    for i in range(len(systems)):
+        if i != 2:
+            assert res[i]["converged"] == 1 and np.array_equal(xs[i], xs0[i])
+
+
+def test_server_refuses_oversized(dc, torch_dev):
+    torch, dev = torch_dev
+    srv = dc.Server(device=0, slots=1, tile=128, pool_bytes=1 << 20)
+    try:
+        a = torch.eye(1024, dtype=torch.float64, device=dev)
+        b = torch.ones(1024, 1, dtype=torch.float64, device=dev)
+        with pytest.raises(dc.DagcholError):
+            srv.submit(a, b, torch.zeros_like(b))
+        assert srv.progress() == ([], 0)
+    finally:
+        srv.close()
