@@ -235,6 +235,30 @@ int dc_trace_get(dc_runtime *rt, int64_t t, int64_t *start_ns, int64_t *end_ns,
  * pointer may be NULL. */
 int dc_last_launch(dc_runtime *rt, double *build_ms, int64_t *units, int32_t *workers);
 
+/* Per-kernel timing.  While enabled, every launch of the two executor
+ * kernels is bracketed by HIP events on the stream it is launched on; each
+ * completed graph adds the measured durations and the algorithmic work of
+ * the units those launches ran.  Algorithmic work per task (the operation's
+ * definition, independent of how the kernel computes it): POTRF m^3/3 + m^2/2
+ * + m/6 flop; TRSM and the solve TRSMs m n^2; SYRK m(m+1)k; GEMM and the
+ * solve GEMMs 2mnk; RESID 2 m^2 r; AXPY 2mn; SCAL m; CAST 0.  Bytes: every
+ * operand read once and every output written once at its storage precision
+ * (lower triangles for POTRF, SYRK's C and the L of the TRSMs). */
+typedef struct {
+  int64_t launches;   /* kernel launches timed */
+  double ms;          /* sum of their durations */
+  double flops;       /* algorithmic flops of the units they ran */
+  double bytes;       /* algorithmic bytes of the units they ran */
+} dc_kernel_stat;
+typedef struct {
+  dc_kernel_stat panel;   /* POTRF, TRSM, solve, cast, residual, axpy, scal */
+  dc_kernel_stat gemm;    /* GEMM and SYRK */
+} dc_kernel_stats;
+/* enable != 0 switches timing on and clears the totals; 0 switches it off. */
+int dc_kernel_timing(dc_runtime *rt, int enable);
+/* Totals over the graphs completed since timing was enabled. */
+int dc_kernel_stats_get(dc_runtime *rt, dc_kernel_stats *out);
+
 /* ------------------------------------------------ high-level operations */
 
 /* Each of these only submits tasks through dc_task_submit (the matrix must

@@ -159,6 +159,7 @@ extern "C" int dc_shutdown(dc_runtime *rt) {
     err = dc_wait_all(rt);
     free_device(rt);
     for (hipEvent_t e : rt->events) hipEventDestroy(e);
+    for (hipEvent_t e : rt->tevents) hipEventDestroy(e);
     if (rt->side) hipStreamDestroy(rt->side);
     if (rt->own_stream) hipStreamDestroy(rt->stream);
   }
@@ -636,6 +637,16 @@ static int finalize(dc_runtime *rt) {
     Handle &h = rt->handles[f.slot_roots[s] - 1];
     h.info = info;
   }
+  for (const Inflight::Timed &t : f.timed) {
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, rt->tevents[t.b], rt->tevents[t.e]) != hipSuccess) return -EIO;
+    dc_kernel_stat &k = t.cls ? rt->kstats.gemm : rt->kstats.panel;
+    k.launches += 1;
+    k.ms += ms;
+    k.flops += t.flops;
+    k.bytes += t.bytes;
+  }
+  f.timed.clear();
   if (f.trace_off) {
     rt->trace_host.resize(3 * (size_t)f.ntasks);
     e = hipMemcpy(rt->trace_host.data(), (char *)rt->arena_dev + f.trace_off,
@@ -646,6 +657,33 @@ static int finalize(dc_runtime *rt) {
     rt->trace_kind = f.kinds;
   }
   return status;
+}
+
+// Algorithmic work of a task: the operation's flop count and the bytes of
+// reading every operand once and writing every output once.
+static double esize(int t) { return t == T_F64 ? 8.0 : t == T_F32 ? 4.0 : 2.0; }
+static void task_work(const TaskDesc &d, double *flops, double *bytes) {
+  const double m = d.m, n = d.n, k = d.k;
+  const double tri_m = m * (m + 1) / 2, tri_n = n * (n + 1) / 2;
+  switch (d.kind) {
+    case K_POTRF: *flops = m * m * m / 3 + m * m / 2 + m / 6; *bytes = 2 * 8 * tri_m; break;
+    case K_TRSM: *flops = m * n * n; *bytes = 8 * tri_n + 2 * esize(d.tc) * m * n; break;
+    case K_TRSM_CAST: *flops = m * n * n; *bytes = 8 * tri_n + 2 * 4 * m * n + 2 * m * n; break;
+    case K_SYRK: *flops = m * (m + 1) * k; *bytes = esize(d.ta) * m * k + 2 * esize(d.tc) * tri_m; break;
+    case K_GEMM:
+      *flops = 2 * m * n * k;
+      *bytes = esize(d.ta) * m * k + esize(d.tb) * n * k + 2 * esize(d.tc) * m * n;
+      break;
+    case K_TRSM_L: case K_TRSM_LT:
+      *flops = m * m * n; *bytes = esize(d.ta) * tri_m + 2 * 8 * m * n; break;
+    case K_GEMM_RHS_N: case K_GEMM_RHS_T:
+      *flops = 2 * m * n * k; *bytes = esize(d.ta) * m * k + 8 * k * n + 2 * 8 * m * n; break;
+    case K_RESID: *flops = 2 * m * m * n; *bytes = 8 * m * m + 3 * 8 * m * n; break;
+    case K_AXPY: *flops = 2 * m * n; *bytes = 3 * 8 * m * n; break;
+    case K_SCAL: *flops = m; *bytes = 2 * 4 * m; break;
+    case K_CAST: *flops = 0; *bytes = (esize(d.ta) + esize(d.tc)) * m * n; break;
+    default: *flops = 0; *bytes = 0;
+  }
 }
 
 // LDS bytes the level kernel needs for a unit of this task.
@@ -744,11 +782,19 @@ extern "C" int dc_flush(dc_runtime *rt) {
   auto is_gemm = [](const TaskDesc &d) { return d.kind == K_GEMM || d.kind == K_SYRK; };
   int64_t total_units = 0;
   std::vector<int64_t> pcount(nl, 0), gcount(nl, 0), lcount(nl, 0);
+  const bool timing = rt->ktiming;
+  std::vector<double> wflops(timing ? 2 * nl : 0, 0.0), wbytes(timing ? 2 * nl : 0, 0.0);
   for (int64_t t = 0; t < nt; ++t) {
     const TaskDesc &d = rt->tasks[t].desc;
     total_units += d.nunits;
     (is_gemm(d) ? gcount : pcount)[level[t]] += d.nunits;
     lcount[level[t]] += d.nunits;
+    if (timing) {
+      double fl, by;
+      task_work(d, &fl, &by);
+      wflops[2 * level[t] + is_gemm(d)] += fl;
+      wbytes[2 * level[t] + is_gemm(d)] += by;
+    }
   }
   if (total_units >= INT32_MAX) { drop(); return -ENOMEM; }
   const int nslots_roots = (int)rt->slot_roots.size();
@@ -824,7 +870,18 @@ extern "C" int dc_flush(dc_runtime *rt) {
   if (e != hipSuccess) { drop(); return fail_hip(e, "hipMemcpyAsync(graph)"); }
   char *db = (char *)rt->arena_dev;
   int max_workers = 0;
-  size_t nevents = 0;
+  size_t nevents = 0, ntev = 0;
+  std::vector<Inflight::Timed> timed;
+  // a timing event pair around one launch on stream st
+  auto tev = [&](hipStream_t st) -> size_t {
+    while (rt->tevents.size() <= ntev) {
+      hipEvent_t ev;
+      if (hipEventCreate(&ev) != hipSuccess) return SIZE_MAX;
+      rt->tevents.push_back(ev);
+    }
+    if (hipEventRecord(rt->tevents[ntev], st) != hipSuccess) return SIZE_MAX;
+    return ntev++;
+  };
   for (int64_t L = 0; L < nl; ++L) {
     LevelArgs a;
     a.desc = (const TaskDesc *)(db + o_desc);
@@ -858,15 +915,27 @@ extern "C" int dc_flush(dc_runtime *rt) {
       a.begin = lbegin[L];
       a.count = pcount[L];
       a.counter = (unsigned long long *)(db + o_cnt) + 2 * L;
+      const size_t tb = timing ? tev(pstream) : 0;
       int le = dcx_launch_level(a, pworkers, llds[L], pstream);
       if (le != 0) { fail_hip((hipError_t)le, "level launch"); drop(); return -EIO; }
+      if (timing) {
+        const size_t te = tev(pstream);
+        if (tb == SIZE_MAX || te == SIZE_MAX) { drop(); return -EIO; }
+        timed.push_back({tb, te, 0, wflops[2 * L], wbytes[2 * L]});
+      }
     }
     if (hasg) {
       a.begin = gbegin[L];
       a.count = gcount[L];
       a.counter = (unsigned long long *)(db + o_cnt) + 2 * L + 1;
+      const size_t tb = timing ? tev(rt->stream) : 0;
       int le = dcx_launch_gemm(a, gworkers, rt->stream);
       if (le != 0) { fail_hip((hipError_t)le, "gemm launch"); drop(); return -EIO; }
+      if (timing) {
+        const size_t te = tev(rt->stream);
+        if (tb == SIZE_MAX || te == SIZE_MAX) { drop(); return -EIO; }
+        timed.push_back({tb, te, 1, wflops[2 * L + 1], wbytes[2 * L + 1]});
+      }
     }
     if (hasp && hasg) {
       // join
@@ -887,6 +956,7 @@ extern "C" int dc_flush(dc_runtime *rt) {
   f.slot_factor = rt->slot_factor;
   f.kinds.resize(nt);
   for (int64_t t = 0; t < nt; ++t) f.kinds[t] = rt->tasks[t].desc.kind;
+  f.timed = std::move(timed);
   rt->inflight = true;
   rt->last_units = total_units;
   rt->last_workers = max_workers;
@@ -914,6 +984,19 @@ extern "C" const char *dc_strerror(int err) {
     case -EIO: return "HIP runtime error";
     default: return "unknown error";
   }
+}
+
+extern "C" int dc_kernel_timing(dc_runtime *rt, int enable) {
+  if (!rt) return -EINVAL;
+  rt->ktiming = enable != 0;
+  if (enable) memset(&rt->kstats, 0, sizeof(rt->kstats));
+  return 0;
+}
+
+extern "C" int dc_kernel_stats_get(dc_runtime *rt, dc_kernel_stats *out) {
+  if (!rt || !out) return -EINVAL;
+  *out = rt->kstats;
+  return 0;
 }
 
 // Runtime diagnostics used by the Python layer and the benchmark.

@@ -48,6 +48,9 @@ struct Inflight {
   std::vector<dc_handle> slot_roots;
   std::vector<char> slot_factor;   // slot has a POTRF task in the graph
   std::vector<int32_t> kinds;
+  // timed launches: (begin event, end event, kernel class, flops, bytes)
+  struct Timed { size_t b, e; int cls; double flops, bytes; };
+  std::vector<Timed> timed;
 };
 
 struct dc_runtime {
@@ -55,6 +58,9 @@ struct dc_runtime {
   hipStream_t stream = nullptr;
   hipStream_t side = nullptr;                  // panel units next to GEMM units
   std::vector<hipEvent_t> events;              // fork/join events, reused per flush
+  bool ktiming = false;                        // per-kernel timing enabled
+  std::vector<hipEvent_t> tevents;             // timing events, reused per flush
+  dc_kernel_stats kstats{};
   bool own_stream = false;
   int num_cus = 0;
   int default_workers = 1;

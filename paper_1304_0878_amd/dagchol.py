@@ -51,6 +51,15 @@ class dc_ir_report(ctypes.Structure):
                 ("refine_ms", ctypes.c_double)]
 
 
+class dc_kernel_stat(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_int64), ("ms", ctypes.c_double),
+                ("flops", ctypes.c_double), ("bytes", ctypes.c_double)]
+
+
+class dc_kernel_stats(ctypes.Structure):
+    _fields_ = [("panel", dc_kernel_stat), ("gemm", dc_kernel_stat)]
+
+
 class dc_server_config(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int), ("slots", ctypes.c_int), ("pool_bytes", ctypes.c_size_t),
                 ("tile", ctypes.c_int64), ("upd", ctypes.c_int), ("tol", ctypes.c_double),
@@ -108,6 +117,8 @@ _SIGS = {
                                   ctypes.c_int, ctypes.POINTER(dc_ir_report)]),
     "dc_last_launch": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double), _PI64, _PI32]),
     "dc_potrf_batched": (ctypes.c_int, [_P, _I64, _PH, _PH, _PI64, _PI64]),
+    "dc_kernel_timing": (ctypes.c_int, [_P, ctypes.c_int]),
+    "dc_kernel_stats_get": (ctypes.c_int, [_P, ctypes.POINTER(dc_kernel_stats)]),
     "dc_server_config_default": (None, [ctypes.POINTER(dc_server_config)]),
     "dc_server_create": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.POINTER(dc_server_config)]),
     "dc_server_destroy": (ctypes.c_int, [_P]),
@@ -293,6 +304,15 @@ class Runtime:
         _check(_lib.dc_last_launch(self._ptr, ctypes.byref(b), ctypes.byref(u), ctypes.byref(w)),
                "dc_last_launch")
         return {"build_ms": b.value, "units": u.value, "workers": w.value}
+
+    def dc_kernel_timing(self, enable=True):
+        _check(_lib.dc_kernel_timing(self._ptr, 1 if enable else 0), "dc_kernel_timing")
+
+    def dc_kernel_stats_get(self):
+        st = dc_kernel_stats()
+        _check(_lib.dc_kernel_stats_get(self._ptr, ctypes.byref(st)), "dc_kernel_stats_get")
+        return {k: {f: getattr(getattr(st, k), f) for f, _ in dc_kernel_stat._fields_}
+                for k in ("panel", "gemm")}
 
     # -- high level
     def dc_potrf(self, a, tile):
