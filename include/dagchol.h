@@ -87,7 +87,9 @@ typedef enum { DC_F64 = 0, DC_F32 = 1, DC_BF16 = 2 } dc_dtype;
  *   DC_CAST       (S:R, D:W)        D <- S converted to D's dtype (round to
  *                                   nearest even), same shape.
  *   DC_RESID      (A:R, X:R, B:R, R:W)  R <- B - A X, A symmetric given by
- *                                   its lower triangle, FP64.
+ *                                   its lower triangle, FP64; each row is a
+ *                                   compensated dot product (error-free
+ *                                   products and sums), rounded once.
  *   DC_AXPY       (D:R, X:RW)       X <- X + D, FP64 matrices of one shape.
  *   DC_TRSM_CAST  (L:R, X:RW, S:W)  TRSM on an FP32 tile X that also writes
  *                                   S = BF16(X) (round to nearest even).
@@ -279,13 +281,17 @@ int dc_potrs(dc_runtime *rt, dc_handle L, dc_handle B, int64_t tile);
  * FP64, lower triangle) is left unchanged.  upd selects the precision of the
  * SYRK/GEMM updates (DC_F64, DC_F32 or DC_BF16); the diagonal POTRF tasks
  * stay FP64 and off-diagonal factor tiles are stored in FP32 when upd is not
- * DC_F64.  x0 = solve(b); then r = b - A x (FP64), d = solve(r), x += d
- * until ||d||_inf <= tol ||x||_inf for every column, stagnation
- * (||d_i|| > 0.5 ||d_{i-1}||) or maxit steps.  If the factor breaks down or
- * refinement does not converge, the next wider precision is used (BF16 ->
- * FP32 -> FP64).  B and X are n x r FP64; X receives the solution. */
+ * DC_F64.  x0 = solve(b); then r = b - A x (FP64 storage, computed as a
+ * compensated dot product per row, as accurate as twice-FP64 arithmetic
+ * rounded once), d = solve(r), x += d, until ||d||_inf <= tol ||x||_inf for
+ * every column (converged; that last d is still added), stagnation
+ * (||d_i|| > 0.5 ||d_{i-1}|| in some column; d_i is not added) or maxit
+ * steps.  If the factor breaks down or refinement does not converge,
+ * the next wider precision is used (BF16 -> FP32 -> FP64).  B and X are
+ * n x r FP64; X receives the solution. */
 typedef struct {
-  int iterations;        /* refinement steps of the precision that was kept */
+  int iterations;        /* refinement steps before the one that met the
+                            test, with the precision that was kept */
   int converged;         /* 1 if the stopping test was met */
   int final_prec;        /* dc_dtype actually used for the updates */
   int fallbacks;         /* precision changes made */

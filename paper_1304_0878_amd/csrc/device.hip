@@ -14,7 +14,8 @@
 // it.  Tile kernels (right-looking tiled Cholesky; the paper's Section 5.1
 // cites Cholesky as the partitioning idiom):
 //   POTRF  D = L L^T on one diagonal tile (FP64, left-looking 16-column
-//          panels: MFMA panel update, then column-by-column sqrt/divide).
+//          panels: MFMA panel update, one wave factors the diagonal block,
+//          the other rows follow by substitution).
 //   TRSM   X <- X L^{-T} on 16-row slabs of a panel tile kept in LDS (FP64
 //          arithmetic; FP32 tiles are widened on load and rounded on store,
 //          optionally also writing a BF16 copy).
@@ -33,6 +34,7 @@ namespace {
 constexpr int NT = 256;                    // threads per workgroup
 constexpr int LDS_DOUBLES = PANEL_LDS_DOUBLES;     // largest LDS need of a unit
 
+static_assert(NT == 256 && PANEL == 16 && TRSM_ROWS == 16, "stage16 maps 256 threads on 16 rows");
 static_assert(2 * TRSM_ROWS * (MAX_TILE + 2) + PANEL * (PANEL + 1) <= LDS_DOUBLES, "trsm lds");
 static_assert(PANEL * (MAX_TILE + 2) + PANEL * (PANEL + 1) + 8 <= LDS_DOUBLES, "potrf lds");
 
@@ -47,6 +49,40 @@ template <typename T> using gptr = __attribute__((address_space(1))) T *;
 
 __device__ __forceinline__ double mfma44(double a, double b, double c) {
   return __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, c, 0, 0, 0);
+}
+
+// Copies a block of 16 rows x ncols of a row-major global matrix into LDS
+// (row stride dstride); rows at or beyond nvalid are zero.  Thread t takes
+// row t/16 and columns t%16 + 16i, so each wave reads four 128-byte row
+// segments per instruction, and keeps eight loads in flight before its LDS
+// stores.  TS is the storage type of the source (double or float).
+template <typename TS>
+__device__ __forceinline__ void stage16(double *dst, int dstride, gptr<const TS> src, int64_t ld,
+                                        int nvalid, int ncols) {
+  const int r = threadIdx.x >> 4, c = threadIdx.x & 15;
+  gptr<const TS> sp = src + (int64_t)(r < nvalid ? r : 0) * ld;
+  const bool ok = r < nvalid;
+  for (int cb = 0; cb < ncols; cb += 128) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int cc = cb + c + 16 * u;
+      v[u] = (ok && cc < ncols) ? (double)sp[cc] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int cc = cb + c + 16 * u;
+      if (cc < ncols) dst[r * dstride + cc] = v[u];
+    }
+  }
+}
+
+// Orders the LDS accesses of one wave (its LDS operations execute in issue
+// order; this keeps the compiler from moving them across the point).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // ------------------------------------------------------------------ TRSM
@@ -78,22 +114,21 @@ __device__ __forceinline__ void run_trsm(const TaskDesc &d, int unit, double *ld
 
   const bool x32 = d.tc == T_F32;
   gfloat *X32 = (gfloat *)d.c + (int64_t)r0 * d.ldc;
-  for (int idx = tid; idx < TRSM_ROWS * nb; idx += NT) {
-    const int r = idx / nb, c = idx - r * nb;
-    Xs[r * XS + c] = r < rows ? (x32 ? (double)X32[(int64_t)r * ldc + c] : X[(int64_t)r * ldc + c])
-                              : 0.0;
-  }
+  if (x32)
+    stage16<float>(Xs, XS, X32, ldc, rows, nb);
+  else
+    stage16<double>(Xs, XS, X, ldc, rows, nb);
   const int nj = (nb + PANEL - 1) / PANEL;
   for (int J = 0; J < nj; ++J) {
     const int c0 = PANEL * J;
     const int wj = min(PANEL, nb - c0);
-    for (int idx = tid; idx < PANEL * c0; idx += NT) {
-      const int r = idx / c0, k = idx - r * c0;
-      Lp[r * XS + k] = r < wj ? L[(int64_t)(c0 + r) * ldl + k] : 0.0;
-    }
-    for (int idx = tid; idx < PANEL * PANEL; idx += NT) {
-      const int i = idx / PANEL, j = idx % PANEL;
-      Ljj[i * (PANEL + 1) + j] = (i < wj && j <= i) ? L[(int64_t)(c0 + i) * ldl + c0 + j] : 0.0;
+    // rows c0..c0+15 of L, columns 0..c0+15 (the block left of the diagonal
+    // and the diagonal block itself)
+    stage16<double>(Lp, XS, L + (int64_t)c0 * ldl, ldl, wj, c0 + wj);
+    __syncthreads();
+    {
+      const int i = tid >> 4, j = tid & 15;
+      Ljj[i * (PANEL + 1) + j] = (i < wj && j <= i) ? Lp[i * XS + c0 + j] : 0.0;
     }
     __syncthreads();
     if (c0 > 0) {
@@ -149,11 +184,12 @@ __device__ __forceinline__ void run_trsm(const TaskDesc &d, int unit, double *ld
 // (1) D[c0:, c0:c0+16] -= D[c0:, :c0] D[c0:c0+16, :c0]^T with MFMA: the 16
 // pivot rows are staged in LDS, each wave takes every fourth 16-row group
 // and keeps up to eight groups' accumulators, the next 16 columns of its
-// rows being loaded while the current ones are multiplied; (2) column by
-// column: the owner of the pivot row forms the pivot, takes its square root
-// (or reports breakdown), publishes its row in LDS, and every thread divides
-// its rows' entries.  Returns 0 or the 1-based local column of the first
-// non-positive pivot.
+// rows being loaded while the current ones are multiplied; (2) the first
+// wave factors the 16x16 diagonal block column by column (square root of
+// each pivot, or breakdown), exchanging pivot rows through LDS inside the
+// wave, and publishes it; after one barrier every thread finishes the rows
+// below the block by substitution.  Returns 0 or the 1-based local column of
+// the first non-positive pivot.
 __device__ __forceinline__ int run_potrf(const TaskDesc &d, double *lds) {
   const int nb = d.m;
   gdouble *D = (gdouble *)d.c;
@@ -179,10 +215,7 @@ __device__ __forceinline__ int run_potrf(const TaskDesc &d, double *lds) {
     const int wj = min(PANEL, nb - c0);
     const int nrows = nb - c0;
     if (c0 > 0) {
-      for (int idx = tid; idx < PANEL * c0; idx += NT) {
-        const int r = idx / c0, k = idx - r * c0;
-        Bp[r * BS + k] = r < wj ? D[(int64_t)(c0 + r) * ldd + k] : 0.0;
-      }
+      stage16<double>(Bp, BS, D + (int64_t)c0 * ldd, ldd, wj, c0);
       __syncthreads();
       const int ngroups = (nrows + 15) / 16;
       double acc[GQ][4];
@@ -242,7 +275,11 @@ __device__ __forceinline__ int run_potrf(const TaskDesc &d, double *lds) {
       }
       __syncthreads();
     }
-    // column-by-column factor of the panel
+    // factor of the panel: (a) the first wave factors the 16x16 diagonal
+    // block, lane j owning row c0 + j, column by column with the finished
+    // pivot rows exchanged through LDS inside the wave (no workgroup
+    // barrier); (b) after one barrier every thread finishes its rows below
+    // the block by substitution with the published block.
     double v[RPT][PANEL];
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
@@ -251,39 +288,55 @@ __device__ __forceinline__ int run_potrf(const TaskDesc &d, double *lds) {
       for (int j = 0; j < PANEL; ++j)
         v[q][j] = (row < nb && j < wj && c0 + j <= row) ? D[(int64_t)row * ldd + c0 + j] : 0.0;
     }
-    if (tid == 0) *flag = 0;
-    __syncthreads();
+    if (w == 0) {
+      int f = 0;
 #pragma unroll
-    for (int j = 0; j < PANEL; ++j) {
-      if (j < wj) {
-        if (tid == j) {   // owner of pivot row c0 + j (slot 0)
-          double s = v[0][j];
+      for (int j = 0; j < PANEL; ++j) {
+        if (j < wj) {
+          if (lane == j) {
+            double s = v[0][j];
 #pragma unroll
-          for (int p = 0; p < j; ++p) s = s - v[0][p] * v[0][p];
-          if (!(s > 0.0)) {
-            *flag = j + 1;
-          } else {
-            v[0][j] = sqrt(s);
+            for (int p = 0; p < j; ++p) s = s - v[0][p] * v[0][p];
+            const bool okp = s > 0.0;
+            v[0][j] = okp ? sqrt(s) : s;
 #pragma unroll
             for (int p = 0; p <= j; ++p) Ds[j * (PANEL + 1) + p] = v[0][p];
+            Ds[j * (PANEL + 1) + PANEL] = okp ? 0.0 : 1.0;
+          }
+          wave_sync();
+          if (Ds[j * (PANEL + 1) + PANEL] != 0.0) {   // same value in every lane
+            f = j + 1;
+            break;
+          }
+          if (lane > j && lane < wj) {
+            double t = v[0][j];
+#pragma unroll
+            for (int p = 0; p < j; ++p) t = t - v[0][p] * Ds[j * (PANEL + 1) + p];
+            v[0][j] = t / Ds[j * (PANEL + 1) + j];
           }
         }
-        __syncthreads();
-        if (*flag) break;
-        const double piv = Ds[j * (PANEL + 1) + j];
+      }
+      if (lane == 0) *flag = f;
+    }
+    __syncthreads();
+    bad = *flag ? c0 + *flag : 0;
+    if (!bad) {
 #pragma unroll
-        for (int q = 0; q < RPT; ++q) {
-          const int row = c0 + tid + NT * q;
-          if (row > c0 + j && row < nb) {
-            double t = v[q][j];
+      for (int q = 0; q < RPT; ++q) {
+        const int row = c0 + tid + NT * q;
+        if (row >= c0 + PANEL && row < nb) {
 #pragma unroll
-            for (int p = 0; p < j; ++p) t = t - v[q][p] * Ds[j * (PANEL + 1) + p];
-            v[q][j] = t / piv;
+          for (int j = 0; j < PANEL; ++j) {
+            if (j < wj) {
+              double t = v[q][j];
+#pragma unroll
+              for (int p = 0; p < j; ++p) t = t - v[q][p] * Ds[j * (PANEL + 1) + p];
+              v[q][j] = t / Ds[j * (PANEL + 1) + j];
+            }
           }
         }
       }
     }
-    bad = *flag ? c0 + *flag : 0;
     if (!bad) {
 #pragma unroll
       for (int q = 0; q < RPT; ++q) {
@@ -565,7 +618,36 @@ __device__ __forceinline__ void run_axpy(const TaskDesc &d, int unit) {
 // rows.  Part 1 (columns j <= i) reads rows of A, part 2 (j > i) reads the
 // rows below the unit; each wave sums a slice and the slices are added in a
 // fixed order.
+// Error-free transformations (Ogita, Rump and Oishi, "Accurate sum and dot
+// product", 2005): a*b = p + e exactly (one FMA), and a + b = s + t exactly.
+__device__ __forceinline__ void two_prod(double a, double b, double &p, double &e) {
+  p = a * b;
+  e = __builtin_fma(a, b, -p);
+}
+__device__ __forceinline__ void two_sum(double a, double b, double &s, double &t) {
+#pragma clang fp contract(off)
+  s = a + b;
+  const double z = s - a;
+  t = (a - (s - z)) + (b - z);
+}
+// (s, c) += (s2, c2): compensated sum of two partial sums.
+__device__ __forceinline__ void add2(double &s, double &c, double s2, double c2) {
+#pragma clang fp contract(off)
+  double t;
+  two_sum(s, s2, s, t);
+  c = c + (c2 + t);
+}
+
+// R <- B - A X with A symmetric (lower triangle stored); unit = 64 rows.
+// Each row is a compensated dot product (Dot2 of the reference above: the
+// products and sums are carried with their exact rounding errors), so the
+// residual is as accurate as if computed in twice the FP64 precision and
+// then rounded; iterative refinement then converges to a solution accurate
+// to FP64 roundoff rather than to cond(A) times it.  Part 1: each wave takes
+// 16 rows, lanes split the stored row (j <= i); part 2: lane = row, waves
+// split the column below the diagonal (j > i), read coalesced.
 __device__ __forceinline__ void run_resid(const TaskDesc &d, int unit, double *lds) {
+#pragma clang fp contract(off)
   const gdouble *A = (const gdouble *)d.a;
   const gdouble *X = (const gdouble *)d.b;
   const gdouble *Bm = (const gdouble *)d.d;
@@ -573,66 +655,87 @@ __device__ __forceinline__ void run_resid(const TaskDesc &d, int unit, double *l
   const int n = d.m, r = d.n;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int i0 = unit * ROW_UNIT;
-  double *part = lds;   // [2 parts][64 rows][8 cols] + [4 slices][64][8]
-  double *part2 = lds + 2 * 64 * 8;
-  for (int c0 = 0; c0 < r; c0 += 8) {
-    // part 1: each wave handles 16 rows, lanes split j in [0, i]
+  // [64 rows][4 cols] sums and errors of part 1, [4 slices][64][4] of part 2
+  double *ps = lds, *pc = lds + 64 * 4;
+  double *qs = lds + 2 * 64 * 4, *qc = qs + 4 * 64 * 4;
+  for (int c0 = 0; c0 < r; c0 += 4) {
     for (int q = 0; q < 16; ++q) {
       const int ii = w * 16 + q;
       const int i = i0 + ii;
-      double acc[8];
+      double s[4], c[4];
 #pragma unroll
-      for (int c = 0; c < 8; ++c) acc[c] = 0.0;
+      for (int k = 0; k < 4; ++k) s[k] = c[k] = 0.0;
       if (i < n) {
         const gdouble *ar = A + (int64_t)i * d.lda;
         for (int j = lane; j <= i; j += 64) {
           const double av = ar[j];
           const gdouble *xp = X + (int64_t)j * d.ldb + c0;
 #pragma unroll
-          for (int c = 0; c < 8; ++c)
-            if (c0 + c < r) acc[c] += av * xp[c];
+          for (int k = 0; k < 4; ++k)
+            if (c0 + k < r) {
+              double p, e, t;
+              two_prod(av, xp[k], p, e);
+              two_sum(s[k], p, s[k], t);
+              c[k] = c[k] + (t + e);
+            }
         }
       }
 #pragma unroll
-      for (int c = 0; c < 8; ++c) {
-        double v = acc[c];
+      for (int k = 0; k < 4; ++k) {
 #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-        if (lane == 0) part[(0 * 64 + ii) * 8 + c] = v;
+        for (int off = 32; off > 0; off >>= 1) {
+          const double s2 = __shfl_xor(s[k], off), c2 = __shfl_xor(c[k], off);
+          add2(s[k], c[k], s2, c2);
+        }
+        if (lane == 0) {
+          ps[ii * 4 + k] = s[k];
+          pc[ii * 4 + k] = c[k];
+        }
       }
     }
-    // part 2: lane = row of the unit, wave = slice of j > i
     {
       const int ii = lane;
       const int i = i0 + ii;
-      double acc[8];
+      double s[4], c[4];
 #pragma unroll
-      for (int c = 0; c < 8; ++c) acc[c] = 0.0;
+      for (int k = 0; k < 4; ++k) s[k] = c[k] = 0.0;
       if (i < n) {
         for (int j = i0 + 1 + w; j < n; j += 4) {
           if (j > i) {
             const double av = A[(int64_t)j * d.lda + i];
             const gdouble *xp = X + (int64_t)j * d.ldb + c0;
 #pragma unroll
-            for (int c = 0; c < 8; ++c)
-              if (c0 + c < r) acc[c] += av * xp[c];
+            for (int k = 0; k < 4; ++k)
+              if (c0 + k < r) {
+                double p, e, t;
+                two_prod(av, xp[k], p, e);
+                two_sum(s[k], p, s[k], t);
+                c[k] = c[k] + (t + e);
+              }
           }
         }
       }
 #pragma unroll
-      for (int c = 0; c < 8; ++c) part2[(w * 64 + ii) * 8 + c] = acc[c];
+      for (int k = 0; k < 4; ++k) {
+        qs[(w * 64 + ii) * 4 + k] = s[k];
+        qc[(w * 64 + ii) * 4 + k] = c[k];
+      }
     }
     __syncthreads();
     if (tid < 64) {
       const int i = i0 + tid;
       if (i < n) {
 #pragma unroll
-        for (int c = 0; c < 8; ++c) {
-          if (c0 + c < r) {
-            const double s2 = ((part2[(0 * 64 + tid) * 8 + c] + part2[(1 * 64 + tid) * 8 + c]) +
-                               part2[(2 * 64 + tid) * 8 + c]) + part2[(3 * 64 + tid) * 8 + c];
-            const double s = part[(0 * 64 + tid) * 8 + c] + s2;
-            R[(int64_t)i * d.ldc + c0 + c] = Bm[(int64_t)i * d.ldd + c0 + c] - s;
+        for (int k = 0; k < 4; ++k) {
+          if (c0 + k < r) {
+            double s = ps[tid * 4 + k], c = pc[tid * 4 + k];
+#pragma unroll
+            for (int sl = 0; sl < 4; ++sl)
+              add2(s, c, qs[(sl * 64 + tid) * 4 + k], qc[(sl * 64 + tid) * 4 + k]);
+            // r = b - (s + c), with the rounding of b - s kept
+            double h, t;
+            two_sum(Bm[(int64_t)i * d.ldd + c0 + k], -s, h, t);
+            R[(int64_t)i * d.ldc + c0 + k] = h + (t - c);
           }
         }
       }

@@ -205,11 +205,17 @@ extern "C" int dc_posv_ir(dc_runtime *rt, dc_handle A, dc_handle B, dc_handle X,
     int e = submit(rt, DC_CAST, {B, X}, {DC_R, DC_W}, 0);
     if (!e) e = dc_wait_all(rt);
     if (!e) e = solve_into(X);
-    std::vector<double> prev(r, INFINITY);
+    std::vector<double> prev(r, INFINITY), xn(r), dn(r);
     int it = 0;
-    bool converged = false, stagnated = false;
+    bool converged = false;
     double last = 0.0;
+    auto colmax = [&](const std::vector<double> &v, std::vector<double> &out) {
+      std::fill(out.begin(), out.end(), 0.0);
+      for (int64_t i = 0; i < n; ++i)
+        for (int64_t c = 0; c < r; ++c) out[c] = std::max(out[c], std::fabs(v[i * r + c]));
+    };
     while (!e) {
+      // r = b - A x (compensated), d = solve(r)
       e = submit(rt, DC_RESID, {A, X, B, hR}, {DC_R, DC_R, DC_R, DC_W}, 0);
       if (!e) e = dc_wait_all(rt);
       if (!e) e = solve_into(hR);
@@ -220,26 +226,22 @@ extern "C" int dc_posv_ir(dc_runtime *rt, dc_handle A, dc_handle B, dc_handle X,
         e = -EIO;
         break;
       }
+      colmax(hd, dn);
+      colmax(hx, xn);
       bool all_small = true, any_grow = false;
       last = 0.0;
-      std::vector<double> dn(r, 0.0), xn(r, 0.0);
-      for (int64_t i = 0; i < n; ++i)
-        for (int64_t c = 0; c < r; ++c) {
-          dn[c] = std::max(dn[c], std::fabs(hd[i * r + c]));
-          xn[c] = std::max(xn[c], std::fabs(hx[i * r + c]));
-        }
       for (int64_t c = 0; c < r; ++c) {
         if (!(dn[c] <= tol * xn[c])) all_small = false;
         if (it > 0 && dn[c] > 0.5 * prev[c]) any_grow = true;
         last = std::max(last, xn[c] > 0 ? dn[c] / xn[c] : dn[c]);
       }
-      if (any_grow && !all_small) { stagnated = true; break; }
+      if (any_grow && !all_small) break;   // stagnation: d not added
       e = submit(rt, DC_AXPY, {hR, X}, {DC_R, DC_RW}, 0);
       if (!e) e = dc_wait_all(rt);
       if (e) break;
       if (all_small) { converged = true; break; }
-      prev = dn;
       if (++it >= maxit) break;
+      prev = dn;
     }
     dc_matrix_unpartition(rt, hW);
     TRY(e);
@@ -249,7 +251,6 @@ extern "C" int dc_posv_ir(dc_runtime *rt, dc_handle A, dc_handle B, dc_handle X,
     rep->last_update = last;
     rep->final_prec = prec;
     if (converged || prec == DC_F64) return 0;
-    (void)stagnated;
     prec = prec == DC_BF16 ? DC_F32 : DC_F64;
     rep->fallbacks++;
   }

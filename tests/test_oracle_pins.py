@@ -498,3 +498,33 @@ def test_oracle_threads_do_not_change_results():
         outs.append(subprocess.run([sys.executable, "-c", code], env=env, cwd=root,
                                    capture_output=True, text=True, check=True).stdout)
     assert outs[0] == outs[1]
+
+
+def test_refine_cond_1e6_reaches_reference():
+    """With the extended-precision residual, refinement at cond 1e6 ends on
+    the correction test and reaches the long-double-refined reference far
+    inside 1e-10 (a plainly accumulated FP64 residual stalls near
+    cond * u = 1.1e-10 and does not)."""
+    n = 300
+    a = inputs.spd_cond(n, 31, 1e6)
+    bm = inputs.rhs(n, 2, 32)
+    xref = mixed.reference_solution(a, bm, 64)
+    for upd in ("f32", "f64"):
+        l, _ = mixed.mixed_factor(a, 64, upd)
+        x, it, status = mixed.refine(a, bm, l, 64)
+        assert status == "converged", (upd, it, status)
+        assert np.abs(x - xref).max() / np.abs(xref).max() <= 1e-12
+
+
+def test_refine_bf16_factor_at_cond_1e6_does_not_converge():
+    """A BF16-update factor at cond 1e6 is too poor for refinement to
+    contract (cond * u_bf16 >> 1): the oracle reports it unconverged, which
+    is what triggers the fallback to a wider precision."""
+    n = 200
+    a = inputs.spd_cond(n, 33, 1e6)
+    bm = inputs.rhs(n, 1, 34)
+    l, info = mixed.mixed_factor(a, 64, "bf16")
+    if info:
+        return   # breakdown also triggers the fallback
+    _, _, status = mixed.refine(a, bm, l, 64, maxit=10)
+    assert status != "converged"
