@@ -322,7 +322,8 @@ int dc_potrf_batched(dc_runtime *rt, int64_t count, const dc_handle *A, const dc
  * the GPU.  Per request: copy of A into the pool, factorisation (FP64
  * diagonal tiles, off-diagonal updates at precision `upd`), solve and
  * FP64-residual refinement to ||d||_inf <= tol ||x||_inf per column; a
- * breakdown or failed refinement restarts the request with FP64 updates.
+ * breakdown or failed refinement restarts the request with the next wider
+ * update precision (BF16 -> FP32 -> FP64).
  * The server object is driven by one host thread. */
 typedef struct dc_server dc_server;
 

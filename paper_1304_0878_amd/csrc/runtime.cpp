@@ -704,7 +704,7 @@ static double cost_ns(const TaskDesc &d) {
   switch (d.kind) {
     case K_GEMM: return 2.0 * m * n * k / (d.ta == T_F64 ? 200.0 : 400.0);
     case K_SYRK: return m * m * k / (d.ta == T_F64 ? 200.0 : 400.0);
-    case K_TRSM: case K_TRSM_CAST: return m * n * n / 60.0;
+    case K_TRSM: case K_TRSM_CAST: return m * n * n / 20.0;
     case K_POTRF: return m * m * m / 3.0 / 30.0 + 2000.0;
     case K_TRSM_L: case K_TRSM_LT: return m * m * 8.0 / 20.0 + 2000.0;
     case K_GEMM_RHS_N: case K_GEMM_RHS_T: return m * k * 8.0 / 50.0;
@@ -715,11 +715,13 @@ static double cost_ns(const TaskDesc &d) {
 
 // Splits the pending graph into levels.  asap = earliest level (longest
 // chain of predecessors), alap = latest level that still keeps the number of
-// levels at the critical path length; each task goes, in submission order
-// (a topological order), to the level in [max(level of preds) + 1, alap]
-// where it lengthens the estimated level time least.  These are the
-// compiler-style downward/upward ranks of the paper's Section 5.3 used as a
-// static schedule.
+// levels at the critical path length.  Tasks with asap == alap (the critical
+// chains) are fixed at that level first; every other task then goes, in
+// submission order (a topological order), to the level in
+// [max(level of preds) + 1, alap] where it lengthens the estimated level
+// time least.  asap and alap are the downward and upward ranks that the
+// paper's Section 5.3 proposes as compiler-provided scheduling hints, used
+// here as a static schedule.
 static int64_t assign_levels(dc_runtime *rt, int workers, std::vector<int32_t> &level) {
   const int64_t nt = (int64_t)rt->tasks.size();
   std::vector<int32_t> asap(nt, 0), alap(nt, 0);
@@ -738,7 +740,20 @@ static int64_t assign_levels(dc_runtime *rt, int workers, std::vector<int32_t> &
   level.assign(nt, 0);
   const double w = std::max(1, workers);
   const int window = 48;
+  // pass 1: tasks without slack (asap == alap: the critical chains) are
+  // fixed first, so that the levels they occupy are known when the other
+  // tasks choose theirs and can fill the CUs those chains leave idle
   for (int64_t t = 0; t < nt; ++t) {
+    if (asap[t] != alap[t]) continue;
+    const TaskDesc &d = rt->tasks[t].desc;
+    const double c = cost_ns(d);
+    level[t] = asap[t];
+    lsum[asap[t]] += c;
+    lmax[asap[t]] = std::max(lmax[asap[t]], c / std::max(1, d.nunits));
+  }
+  // pass 2: the others in submission order (a topological order)
+  for (int64_t t = 0; t < nt; ++t) {
+    if (asap[t] == alap[t]) continue;
     const Task &k = rt->tasks[t];
     int32_t lo = 0;
     for (int64_t p : k.preds) lo = std::max(lo, level[p] + 1);
@@ -782,12 +797,14 @@ extern "C" int dc_flush(dc_runtime *rt) {
   auto is_gemm = [](const TaskDesc &d) { return d.kind == K_GEMM || d.kind == K_SYRK; };
   int64_t total_units = 0;
   std::vector<int64_t> pcount(nl, 0), gcount(nl, 0), lcount(nl, 0);
+  std::vector<double> pcost(nl, 0.0), gcost(nl, 0.0);
   const bool timing = rt->ktiming;
   std::vector<double> wflops(timing ? 2 * nl : 0, 0.0), wbytes(timing ? 2 * nl : 0, 0.0);
   for (int64_t t = 0; t < nt; ++t) {
     const TaskDesc &d = rt->tasks[t].desc;
     total_units += d.nunits;
     (is_gemm(d) ? gcount : pcount)[level[t]] += d.nunits;
+    (is_gemm(d) ? gcost : pcost)[level[t]] += cost_ns(d);
     lcount[level[t]] += d.nunits;
     if (timing) {
       double fl, by;
@@ -896,7 +913,12 @@ extern "C" int dc_flush(dc_runtime *rt) {
       int per_cu = 1;
       dcx_level_occupancy(llds[L], &per_cu);
       pworkers = (int)std::min<int64_t>(pcount[L], (int64_t)cus * std::max(1, per_cu));
-      if (hasg) pworkers = std::min(pworkers, std::max(1, cus / 2));
+      if (hasg) {
+        // CUs shared in proportion to the estimated work of the two kernels
+        const double share = pcost[L] / std::max(1.0, pcost[L] + gcost[L]);
+        const int want = std::max(1, (int)std::ceil(share * cus));
+        pworkers = std::min(pworkers, std::min(want, cus - 1));
+      }
     }
     int gworkers = hasg ? (int)std::min<int64_t>(gcount[L], std::max(1, cus - pworkers)) : 0;
     hipStream_t pstream = rt->stream;

@@ -15,7 +15,7 @@
 // off-diagonal tiles FP32 with FP32 or BF16 updates, or all FP64), solve,
 // then refine with the FP64 residual r = b - A x until ||d|| <= tol ||x||
 // (per column) or stagnation; a breakdown or a failed refinement restarts the
-// request with FP64 updates.  Every step only submits tasks through
+// request with the next wider update precision (BF16 -> FP32 -> FP64).  Every step only submits tasks through
 // dc_task_submit and flushes.
 #include <errno.h>
 #include <hip/hip_runtime.h>
@@ -297,10 +297,11 @@ int start(dc_server *srv, Slot &s, const Request &q, size_t off, size_t bytes) {
   return e;
 }
 
-// Restart with FP64 updates (after a breakdown or a failed refinement).
-void restart_fp64(dc_server *srv, Slot &s) {
+// Restart with the next wider update precision (BF16 -> FP32 -> FP64) after
+// a breakdown or a failed refinement.
+void restart_wider(dc_server *srv, Slot &s) {
   Request q = s.req;
-  q.prec = DC_F64;
+  q.prec = q.prec == DC_BF16 ? DC_F32 : DC_F64;
   q.restarts += 1;
   release_slot(srv, s);
   srv->waiting.push_front(q);
@@ -316,7 +317,7 @@ int step(dc_server *srv, Slot &s) {
       int64_t info = 0;
       dc_get_info(s.rt, s.hA, &info);
       if (info != 0) {
-        if (s.req.prec != DC_F64) { restart_fp64(srv, s); return 0; }
+        if (s.req.prec != DC_F64) { restart_wider(srv, s); return 0; }
         finish(srv, s, 0, 0);
         return 0;
       }
@@ -360,7 +361,7 @@ int step(dc_server *srv, Slot &s) {
         s.last = std::max(s.last, xn[k] > 0 ? dn[k] / xn[k] : dn[k]);
       }
       if (grow && !small) {
-        if (s.req.prec != DC_F64) { restart_fp64(srv, s); return 0; }
+        if (s.req.prec != DC_F64) { restart_wider(srv, s); return 0; }
         finish(srv, s, 0, 0);
         return 0;
       }
@@ -390,7 +391,7 @@ int step(dc_server *srv, Slot &s) {
     case P_FINISH: {
       TRY(dc_wait_all(s.rt));
       const bool conv = s.converged;
-      if (!conv && s.req.prec != DC_F64) { restart_fp64(srv, s); return 0; }
+      if (!conv && s.req.prec != DC_F64) { restart_wider(srv, s); return 0; }
       finish(srv, s, 0, conv ? 1 : 0);
       return 0;
     }

@@ -8,8 +8,9 @@ Bars:
     changes when its units run, not what they compute);
   * with a pool that holds one workspace at a time, requests are admitted
     one after another and all complete;
-  * a non-SPD request reports its breakdown column, restarts once in FP64,
-    and leaves the other requests' results bit-identical;
+  * a non-SPD request reports its breakdown column, ends in FP64 after
+    restarting with FP64 updates, and leaves the other requests' results
+    bit-identical;
   * a request whose FP64 workspace can never fit is refused at submission.
 """
 import numpy as np
@@ -70,7 +71,13 @@ def test_server_solutions_match_oracle(dc, torch_dev, upd):
     res, xs = _serve(dc, torch_dev, systems, slots=4, tile=128, upd=code)
     for (a, b), r, x in zip(systems, res, xs):
         assert r["status"] == 0 and r["converged"] == 1 and r["info"] == 0, r
-        assert r["final_prec"] == code and r["restarts"] == 0, r
+        if upd == "bf16":
+            # BF16 updates do not contract at cond 1e4 (cond * 2^-9 > 1): the
+            # request restarts with FP32 updates, which do
+            assert r["final_prec"] in (dc.DC_BF16, dc.DC_F32), r
+            assert r["restarts"] == (r["final_prec"] == dc.DC_F32), r
+        else:
+            assert r["final_prec"] == code and r["restarts"] == 0, r
         assert r["arrival"] <= r["admitted"] <= r["completed"]
         xref = mixed.reference_solution(a, b, 128)
         assert np.abs(x - xref).max() / np.abs(xref).max() <= 1e-10, r
@@ -89,8 +96,14 @@ def test_server_small_pool_admits_one_at_a_time(dc, torch_dev):
     n = 500
     tile = 128
     t = (n + tile - 1) // tile
-    fp32 = t * tile * tile * 8 + n * n * 4 + n * 3 * 8 + 4 * 256
-    res, xs = _serve(dc, torch_dev, systems, slots=4, tile=tile, pool_bytes=int(fp32 * 1.5))
+    # workspaces: FP64 diagonal tiles + off-diagonal tiles + residual; the
+    # pool must hold one FP64 workspace (a restart must always fit) but not
+    # two FP32 ones
+    fp32 = t * tile * tile * 8 + n * n * 4 + n * 3 * 8
+    fp64 = t * tile * tile * 8 + n * n * 8 + n * 3 * 8 + 3 * 256
+    assert fp64 < 2 * fp32
+    pool = (fp64 + 2 * fp32) // 2
+    res, xs = _serve(dc, torch_dev, systems, slots=4, tile=tile, pool_bytes=pool)
     res = sorted(res, key=lambda r: r["admitted"])
     for prev, cur in zip(res, res[1:]):
         assert cur["admitted"] >= prev["completed"] - 1e-9
