@@ -77,6 +77,185 @@ def cpu_baseline(target_s):
                       f"A = B B^T/n + 1e-2 I, B iid N(0,1); {dt:.1f} s"}
 
 
+def leg_mixed(torch, dagchol, rt, stream, a0, l64, n, tile, seed):
+    """Time to solution of one right-hand side at the main workload: the FP64
+    factor (already timed) plus its solve, against dc_posv_ir with FP32 and
+    BF16 updates (FP64 diagonal tiles, refinement to ||d|| <= 1e-12 ||x||).
+    Accuracy: each solution's normwise backward error and its distance to the
+    FP64 solution, both on the device."""
+    dev = a0.device
+    g = torch.Generator(device=dev)
+    g.manual_seed(seed + 1000)
+    with torch.cuda.stream(stream):
+        b = torch.randn(n, 1, dtype=torch.float64, device=dev, generator=g)
+        anorm = float(a0.abs().sum(1).max())
+    torch.cuda.synchronize()
+
+    def berr(x):
+        with torch.cuda.stream(stream):
+            r = b - a0 @ x
+            v = float(r.abs().max() / (anorm * x.abs().max() + b.abs().max()))
+        torch.cuda.synchronize()
+        return v
+
+    def timed(fn):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        out = fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1), out
+
+    x64 = b.clone()
+    solve_ms, _ = timed(lambda: dagchol.potrs(rt, l64, x64, tile))
+    res = {"fp64_solve_ms": round(solve_ms, 3), "fp64_backward_error": berr(x64)}
+    for name, code in (("f32", dagchol.DC_F32), ("bf16", dagchol.DC_BF16)):
+        x = torch.zeros_like(b)
+        ms, rep = timed(lambda: dagchol.posv_ir(rt, a0, b, x, tile, upd=code, tol=1e-12,
+                                                maxit=30))
+        with torch.cuda.stream(stream):
+            dx = float((x - x64).abs().max() / x64.abs().max())
+        torch.cuda.synchronize()
+        res[name] = {"time_to_solution_ms": round(ms, 3),
+                     "fp64_equivalent_gflops": round(flops_potrf(n) / (ms * 1e-3) / 1e9, 1),
+                     "factor_ms": round(rep["factor_ms"], 3), "refine_ms": round(rep["refine_ms"], 3),
+                     "iterations": rep["iterations"], "converged": rep["converged"],
+                     "final_update_precision": {0: "f64", 1: "f32", 2: "bf16"}[rep["final_prec"]],
+                     "fallbacks": rep["fallbacks"], "backward_error": berr(x),
+                     "rel_diff_to_fp64_solution": dx}
+    return res
+
+
+def leg_batched(torch, dagchol, dev, seed, count, reps):
+    """One graph factoring and solving `count` SPD matrices (n uniform in
+    [16, 512], 1-4 right-hand sides, A = B B^T + n I with B uniform in
+    [-1, 1]) in FP64; tiles from the measured tuning cache when present."""
+    import numpy as np
+    from paper_1304_0878_amd import tune
+    rng = np.random.default_rng(seed)
+    ns = [int(v) for v in rng.integers(16, 513, count)]
+    rs = [int(v) for v in rng.integers(1, 5, count)]
+    cache = tune.load()
+    tiles = tune.tiles_for(ns, cache) if cache else [0 if v <= 128 else 128 for v in ns]
+    g = torch.Generator(device=dev)
+    g.manual_seed(seed)
+    mats, rhs, keep_a, keep_b = [], [], [], []
+    for n_i, r_i in zip(ns, rs):
+        bm = torch.rand(n_i, n_i, dtype=torch.float64, device=dev, generator=g) * 2 - 1
+        a_i = bm @ bm.T
+        a_i.diagonal().add_(n_i)
+        keep_a.append(a_i)
+        keep_b.append(torch.randn(n_i, r_i, dtype=torch.float64, device=dev, generator=g))
+        mats.append(torch.empty_like(a_i))
+        rhs.append(torch.empty_like(keep_b[-1]))
+    torch.cuda.synchronize()
+    rt = dagchol.Runtime(device=0)
+    ha = [rt.register_tensor(m) for m in mats]
+    hb = [rt.register_tensor(v) for v in rhs]
+    times = []
+    for rep in range(reps + 1):
+        for m, k in zip(mats, keep_a):
+            m.copy_(k)
+        for v, k in zip(rhs, keep_b):
+            v.copy_(k)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        infos = rt.dc_potrf_batched(ha, hb, tiles)
+        torch.cuda.synchronize()
+        if rep:
+            times.append(time.perf_counter() - t)
+        if any(infos):
+            raise RuntimeError("batched factorisation broke down")
+    for h in hb + ha:
+        rt.dc_unregister(h)
+    rt.close()
+    # accuracy of a sample: normwise backward error of the solutions
+    worst = 0.0
+    for i in range(0, count, max(1, count // 64)):
+        r = keep_b[i] - keep_a[i] @ rhs[i]
+        worst = max(worst, float(r.abs().max() / (keep_a[i].abs().sum(1).max() * rhs[i].abs().max()
+                                                  + keep_b[i].abs().max())))
+    ms = sorted(times)[len(times) // 2] * 1e3
+    flop = sum(flops_potrf(v) + 2.0 * v * v * r for v, r in zip(ns, rs))
+    return {"matrices": count, "median_ms": round(ms, 3),
+            "matrices_per_s": round(count / (ms * 1e-3), 1),
+            "gflops": round(flop / (ms * 1e-3) / 1e9, 1),
+            "tiles": "tuning cache" if cache else "rule: whole matrix up to 128, else 128",
+            "worst_backward_error_sample": worst,
+            "note": "FP64; one host call = graph build + upload + all level launches + wait"}
+
+
+def leg_serving(torch, dagchol, dev, seed, nreq, nmax):
+    """Open-loop serving: requests (n log-uniform in [32, nmax], 1-8
+    right-hand sides, cond <= 1e2..1e6) drawn from a device-resident pool of
+    matrices.  The saturated throughput of the FP64 path is measured first
+    (all requests at t = 0); both paths then serve a Poisson arrival stream
+    at 0.7 times that rate.  Latency = completion - arrival."""
+    import math as _m
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    pool = []
+    g = torch.Generator(device=dev)
+    g.manual_seed(seed + 7)
+    for i in range(24):
+        n_i = int(round(_m.exp(rng.uniform(_m.log(32), _m.log(nmax)))))
+        kappa = 10.0 ** rng.uniform(2, 6)
+        a_i, _, _ = make_spd(torch, n_i, seed * 100 + i, kappa, dev)
+        pool.append(a_i)
+    reqs = []
+    for i in range(nreq):
+        a_i = pool[int(rng.integers(0, len(pool)))]
+        r_i = int(rng.integers(1, 9))
+        b_i = torch.randn(a_i.shape[0], r_i, dtype=torch.float64, device=dev, generator=g)
+        reqs.append((a_i, b_i, torch.zeros_like(b_i)))
+    torch.cuda.synchronize()
+    flop = sum(flops_potrf(a.shape[0]) + 4.0 * a.shape[0] ** 2 * b.shape[1] for a, b, _ in reqs)
+
+    def serve(upd, arrivals):
+        srv = dagchol.Server(device=0, slots=8, pool_bytes=96 << 30, tile=256, upd=upd,
+                             tol=1e-12, maxit=30)
+        t0 = srv.now()
+        done, i = [], 0
+        while len(done) < nreq:
+            now = srv.now() - t0
+            while i < nreq and arrivals[i] <= now:
+                a_i, b_i, x_i = reqs[i]
+                srv.submit(a_i, b_i, x_i, arrival=t0 + arrivals[i])
+                i += 1
+            got, _ = srv.progress()
+            done += got
+        srv.close()
+        lat = sorted(d["completed"] - d["arrival"] for d in done)
+        span = max(d["completed"] for d in done) - (t0 + arrivals[0])
+        bad = [d for d in done if d["status"] != 0 or not d["converged"]]
+        return {"solves_per_s": round(nreq / span, 2),
+                "p50_ms": round(lat[len(lat) // 2] * 1e3, 2),
+                "p99_ms": round(lat[min(len(lat) - 1, int(0.99 * len(lat)))] * 1e3, 2),
+                "unconverged_or_failed": len(bad),
+                "restarts": sum(d["restarts"] for d in done),
+                "gflops": round(flop / span / 1e9, 1)}
+
+    zero = [0.0] * nreq
+    sat64 = serve(dagchol.DC_F64, zero)
+    sat32 = serve(dagchol.DC_F32, zero)
+    lam = 0.7 * sat64["solves_per_s"]
+    gaps = rng.exponential(1.0 / lam, nreq)
+    arr = list(np.cumsum(gaps) - gaps[0])
+    open64 = serve(dagchol.DC_F64, arr)
+    open32 = serve(dagchol.DC_F32, arr)
+    worst = 0.0
+    for a_i, b_i, x_i in reqs[:: max(1, nreq // 32)]:
+        r = b_i - a_i @ x_i
+        worst = max(worst, float(r.abs().max() / (a_i.abs().sum(1).max() * x_i.abs().max()
+                                                  + b_i.abs().max())))
+    return {"requests": nreq, "n_range": [32, nmax], "pool_matrices": len(pool),
+            "arrival_rate_per_s": round(lam, 2),
+            "saturated": {"fp64": sat64, "mixed_f32": sat32},
+            "open_loop": {"fp64": open64, "mixed_f32": open32},
+            "worst_backward_error_sample": worst}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -88,6 +267,11 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--legs", default="mixed,batched,serving",
+                    help="extra measurements after the FP64 factorisation (comma list, or none)")
+    ap.add_argument("--batch-count", type=int, default=10000)
+    ap.add_argument("--serve-requests", type=int, default=200)
+    ap.add_argument("--serve-nmax", type=int, default=16384)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -143,7 +327,20 @@ def main():
         eta = float(torch.linalg.matrix_norm(r) / torch.linalg.matrix_norm(az))
         del low
     torch.cuda.synchronize()
+    legs = [v for v in args.legs.split(",") if v and v != "none"]
+    extra = {}
+    if "mixed" in legs:
+        extra["mixed_precision"] = leg_mixed(torch, dagchol, rt, stream, a0, a, n, tile, args.seed)
     rt.close()
+    del a
+    torch.cuda.empty_cache()
+    if "batched" in legs:
+        extra["batched"] = leg_batched(torch, dagchol, dev, args.seed, args.batch_count, 3)
+    if "serving" in legs:
+        del a0
+        torch.cuda.empty_cache()
+        extra["serving"] = leg_serving(torch, dagchol, dev, args.seed, args.serve_requests,
+                                       args.serve_nmax)
 
     # roofline of the dominant kernel (GEMM/SYRK updates): its algorithmic
     # flops per launch over its average launch duration
@@ -182,6 +379,7 @@ def main():
                          "tflops": round(pk["flops"] / max(pk["ms"], 1e-9) * 1e-9, 3)},
         "check": {"backward_error_probe": eta},
     }
+    out.update(extra)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     print(json.dumps(out), flush=True)

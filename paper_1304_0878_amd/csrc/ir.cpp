@@ -34,6 +34,20 @@ int submit(dc_runtime *rt, dc_kind k, std::initializer_list<dc_handle> h,
   return dc_task_submit(rt, k, (int)hb.size(), hb.data(), mb.data(), cl, cls, prio);
 }
 
+// Copies an n x r row-major device matrix with leading dimension ld into a
+// dense host array; strided copies go in blocks of rows (rectangular copies
+// of very many rows are not accepted by the runtime).
+hipError_t copy_rows_to_host(double *dst, const double *src, int64_t ld, int64_t n, int64_t r) {
+  if (ld == r) return hipMemcpy(dst, src, (size_t)n * r * 8, hipMemcpyDeviceToHost);
+  for (int64_t i0 = 0; i0 < n; i0 += 4096) {
+    const int64_t rows = std::min<int64_t>(4096, n - i0);
+    const hipError_t e = hipMemcpy2D(dst + i0 * r, r * 8, src + i0 * ld, ld * 8, r * 8, rows,
+                                     hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 struct Scratch {
   void *ptr = nullptr;
   size_t bytes = 0;
@@ -123,6 +137,11 @@ extern "C" int dc_posv_ir(dc_runtime *rt, dc_handle A, dc_handle B, dc_handle X,
       !(tol > 0) || maxit < 0 || (upd != DC_F64 && upd != DC_F32 && upd != DC_BF16))
     return -EINVAL;
   if (pa->partitioned || pb->partitioned || px->partitioned) return -EBUSY;
+  // registering the workspace below may move the handle storage: keep what
+  // is needed of X, and do not use the handle pointers afterwards
+  const double *const xptr = (const double *)px->ptr;
+  const int64_t xld = px->ld;
+  pa = pb = px = nullptr;
   dc_ir_report local;
   memset(&local, 0, sizeof(local));
   if (!rep) rep = &local;
@@ -220,10 +239,19 @@ extern "C" int dc_posv_ir(dc_runtime *rt, dc_handle A, dc_handle B, dc_handle X,
       if (!e) e = dc_wait_all(rt);
       if (!e) e = solve_into(hR);
       if (e) break;
-      if (hipMemcpy(hd.data(), base + o_r, hd.size() * 8, hipMemcpyDeviceToHost) != hipSuccess ||
-          hipMemcpy2D(hx.data(), r * 8, px->ptr, px->ld * 8, r * 8, n, hipMemcpyDeviceToHost) !=
-              hipSuccess) {
-        e = -EIO;
+      hipError_t he = hipGetLastError();
+      if (he != hipSuccess) {
+        e = dcx_fail_hip(he, "error pending before the refinement copies");
+        break;
+      }
+      he = hipMemcpy(hd.data(), base + o_r, hd.size() * 8, hipMemcpyDeviceToHost);
+      if (he != hipSuccess) {
+        e = dcx_fail_hip(he, "copy of the correction to the host");
+        break;
+      }
+      he = copy_rows_to_host(hx.data(), xptr, xld, n, r);
+      if (he != hipSuccess) {
+        e = dcx_fail_hip(he, "copy of the solution to the host");
         break;
       }
       colmax(hd, dn);

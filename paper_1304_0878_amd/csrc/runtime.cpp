@@ -31,10 +31,11 @@ using namespace dcx;
 
 static thread_local std::string g_last_error;
 
-static int fail_hip(hipError_t e, const char *what) {
+int dcx_fail_hip(hipError_t e, const char *what) {
   g_last_error = std::string(what) + ": " + hipGetErrorName(e) + " (" + hipGetErrorString(e) + ")";
   return -EIO;
 }
+static int fail_hip(hipError_t e, const char *what) { return dcx_fail_hip(e, what); }
 
 extern "C" const char *dc_last_error(void) { return g_last_error.c_str(); }
 

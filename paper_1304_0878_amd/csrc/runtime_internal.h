@@ -12,6 +12,10 @@
 
 enum HandleKind { HK_VECTOR = 0, HK_MATRIX = 1 };
 
+// Records a HIP error as the thread's last error message (dc_last_error) and
+// returns -EIO.
+int dcx_fail_hip(hipError_t e, const char *what);
+
 struct Handle {
   int kind = HK_MATRIX;
   void *ptr = nullptr;

@@ -186,3 +186,15 @@ def test_posv_ir_not_spd_reports_info(dc, rt, torch_dev):
     assert rep["final_prec"] == dc.DC_F64 and rep["fallbacks"] == 1
     for h in (hx, hb, ha):
         rt.dc_unregister(h)
+
+
+def test_posv_ir_many_tiles(dc, rt, torch_dev):
+    """Thousands of tile handles are created during the call (the handle
+    table grows while the call runs); the solution must still be right."""
+    n, tile, r = 1024, 16, 1
+    a = inputs.spd_cond(n, 41, 1e3)
+    bm = inputs.rhs(n, r, 42)
+    x, rep, _ = _ir(dc, rt, torch_dev, a, bm, tile, dc.DC_F32)
+    xref = mixed.reference_solution(a, bm, 64)
+    assert rep["converged"] == 1, rep
+    assert np.abs(x - xref).max() / np.abs(xref).max() <= 1e-10
