@@ -37,6 +37,7 @@ constexpr int LDS_DOUBLES = PANEL_LDS_DOUBLES;     // largest LDS need of a unit
 static_assert(NT == 256 && PANEL == 16 && TRSM_ROWS == 16, "stage16 maps 256 threads on 16 rows");
 static_assert(2 * TRSM_ROWS * (MAX_TILE + 2) + PANEL * (PANEL + 1) <= LDS_DOUBLES, "trsm lds");
 static_assert(PANEL * (MAX_TILE + 2) + PANEL * (PANEL + 1) + 8 <= LDS_DOUBLES, "potrf lds");
+static_assert(solve_lds_doubles(MAX_TILE) <= LDS_DOUBLES, "solve lds");
 
 // Global-memory views of the tile pointers: descriptors hold generic
 // pointers, and loads through them would otherwise be flat loads (which also
@@ -353,179 +354,258 @@ __device__ __forceinline__ int run_potrf(const TaskDesc &d, double *lds) {
 
 // ----------------------------------------------------------------- solve
 //
-// B (nb x r, FP64) <- L^{-1} B, L (nb x nb) lower.  16-row blocks: the
-// contribution of earlier rows is a reduction split over 16 thread slices
-// and summed in a fixed order; then one thread per RHS column substitutes
-// through the 16x16 diagonal block.
-template <typename TL>
-__device__ __forceinline__ void run_trsm_l(const TaskDesc &d, double *lds) {
+// Forward and backward substitution on one diagonal tile, and the
+// right-hand-side updates between tiles.  FP64 arithmetic; L may be stored
+// in FP64 or FP32.  All sums are split over 16 thread slices and reduced in
+// a fixed order, so results do not depend on scheduling.
+
+// Loads columns c0 .. c0 + rc - 1 (rc <= CW) of the right-hand sides into
+// LDS (row stride BSS), rows nb .. nb16 - 1 zero; eight loads in flight.
+template <int CW>
+__device__ __forceinline__ void solve_stage(double *Bs, const gdouble *Bm, int64_t ldb, int nb,
+                                            int nb16, int c0, int rc) {
+  const int tid = threadIdx.x;
+  for (int base = 0; base < nb16 * CW; base += NT * 8) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int idx = base + tid + NT * u, i = idx / CW, c = idx % CW;
+      v[u] = (i < nb && c < rc) ? Bm[(int64_t)i * ldb + c0 + c] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int idx = base + tid + NT * u, i = idx / CW, c = idx % CW;
+      if (i < nb16) Bs[i * BSS + c] = v[u];
+    }
+  }
+}
+
+// Solves the 16-row block at row i0 (h rows) in the first wave, once the
+// partial sums are in part[row][slice][col]: lane (row q, column group g)
+// reduces its row's slices in a fixed order, then the block is solved one
+// row at a time, x_i = t_i * (1 / l_ii) on lane i shared across its column
+// group, the other rows dropping their terms in x_i.  FORWARD: rows top down,
+// lrow[i] = l_qi; otherwise bottom up with lrow[i] = l_iq.
+template <bool FORWARD>
+__device__ __forceinline__ void solve_block(double *Bs, const double *part, const double *Ljj,
+                                            int i0, int h, int rc) {
+  const int tid = threadIdx.x;
+  if (tid >= 64) return;
+  const int q = tid & 15, g = tid >> 4;
+  double lrow[16];
+#pragma unroll
+  for (int p = 0; p < 16; ++p) lrow[p] = FORWARD ? Ljj[q * 17 + p] : Ljj[p * 17 + q];
+  const double rinv = q < h ? 1.0 / Ljj[q * 17 + q] : 0.0;
+  for (int cb = 0; cb < rc; cb += 4) {
+    const int c = cb + g;
+    double t = 0.0;
+    if (q < h && c < rc) {
+      double sum = 0.0;
+#pragma unroll
+      for (int sq = 0; sq < 16; ++sq) sum += part[(q * 16 + sq) * 16 + c];
+      t = Bs[(i0 + q) * BSS + c] - sum;
+    }
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const int i = FORWARD ? k : 15 - k;
+      if (i < h) {
+        if (q == i) t = t * rinv;
+        const double xi = __shfl(t, (g << 4) + i);
+        if (FORWARD ? q > i : q < i) t = t - lrow[i] * xi;
+      }
+    }
+    if (q < h && c < rc) Bs[(i0 + q) * BSS + c] = t;
+  }
+}
+
+// B (nb x r) <- L^{-1} B (L lower); passes of up to CW columns in LDS.  Per
+// 16-row block: (a) thread (row, slice) sums every 16th earlier term of its
+// row, the row's loads all issued at once, and the block's diagonal part of
+// L goes to LDS; (b, c) the first wave reduces and substitutes.
+template <typename TL, int CW>
+__device__ __forceinline__ void trsm_l_pass(const TaskDesc &d, double *lds, int c0, int rc) {
   const gptr<const TL> L = (const gptr<const TL>)d.a;
   const int64_t ldl = d.lda;
   gdouble *Bm = (gdouble *)d.c;
   const int64_t ldb = d.ldc;
-  const int nb = d.m, r = d.n;
+  const int nb = d.m;
   const int tid = threadIdx.x;
-  double *part = lds;                    // [16 rows][16 slices][16 cols]
-  double *red = lds + 16 * 16 * 16;      // [16 rows][16 cols]
-  for (int c0 = 0; c0 < r; c0 += 16) {
-    const int rc = min(16, r - c0);
-    for (int i0 = 0; i0 < nb; i0 += 16) {
-      const int h = min(16, nb - i0);
-      {
-        const int ri = tid >> 4, sl = tid & 15;
-        double acc[16];
+  const int nb16 = (nb + 15) / 16 * 16;
+  double *Bs = lds;                                // [nb16][BSS]
+  double *part = Bs + nb16 * BSS;                  // [16][16][16]
+  double *Ljj = part + 16 * 16 * 16 + 16 * 16;     // [16][17]
+  const int ri = tid >> 4, sl = tid & 15;
+  solve_stage<CW>(Bs, Bm, ldb, nb, nb16, c0, rc);
+  __syncthreads();
+  for (int i0 = 0; i0 < nb; i0 += 16) {
+    const int h = min(16, nb - i0);
+    const int nu = i0 / 16;   // earlier terms per slice (uniform)
+    double acc[CW];
 #pragma unroll
-        for (int c = 0; c < 16; ++c) acc[c] = 0.0;
-        if (ri < h) {
-          gptr<const TL> lr = L + (int64_t)(i0 + ri) * ldl;
-          for (int p = sl; p < i0; p += 16) {
-            const double lv = (double)lr[p];
-            const gdouble *bp = Bm + (int64_t)p * ldb + c0;
+    for (int c = 0; c < CW; ++c) acc[c] = 0.0;
+    if (ri < h) {
+      gptr<const TL> lr = L + (int64_t)(i0 + ri) * ldl;
+      double lv[MAX_TILE / 16];
 #pragma unroll
-            for (int c = 0; c < 16; ++c)
-              if (c < rc) acc[c] += lv * bp[c];
-          }
-        }
+      for (int u = 0; u < MAX_TILE / 16; ++u) lv[u] = u < nu ? (double)lr[sl + 16 * u] : 0.0;
+      const double ldg = sl <= ri ? (double)lr[i0 + sl] : 0.0;
 #pragma unroll
-        for (int c = 0; c < 16; ++c) part[(ri * 16 + sl) * 16 + c] = acc[c];
-      }
-      __syncthreads();
-      {
-        const int ri = tid >> 4, c = tid & 15;
-        double s = 0.0;
-        for (int sl = 0; sl < 16; ++sl) s += part[(ri * 16 + sl) * 16 + c];
-        red[ri * 16 + c] = s;
-      }
-      __syncthreads();
-      if (tid < rc) {
-        const int c = tid;
-        double y[16];
+      for (int u = 0; u < MAX_TILE / 16; ++u) {
+        if (u < nu) {
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {
-          if (i < h) {
-            double t = Bm[(int64_t)(i0 + i) * ldb + c0 + c] - red[i * 16 + c];
-            gptr<const TL> lr = L + (int64_t)(i0 + i) * ldl + i0;
-#pragma unroll
-            for (int p = 0; p < i; ++p) t = t - (double)lr[p] * y[p];
-            y[i] = t / (double)lr[i];
-            Bm[(int64_t)(i0 + i) * ldb + c0 + c] = y[i];
-          }
+          for (int c = 0; c < CW; ++c) acc[c] += lv[u] * Bs[(sl + 16 * u) * BSS + c];
         }
       }
-      __syncthreads();
+      Ljj[ri * 17 + sl] = ldg;
     }
+#pragma unroll
+    for (int c = 0; c < CW; ++c) part[(ri * 16 + sl) * 16 + c] = acc[c];
+    __syncthreads();
+    solve_block<true>(Bs, part, Ljj, i0, h, rc);
+    __syncthreads();
+  }
+  for (int idx = tid; idx < nb * CW; idx += NT) {
+    const int i = idx / CW, c = idx % CW;
+    if (c < rc) Bm[(int64_t)i * ldb + c0 + c] = Bs[i * BSS + c];
+  }
+  __syncthreads();
+}
+
+template <typename TL>
+__device__ __forceinline__ void run_trsm_l(const TaskDesc &d, double *lds) {
+  for (int c0 = 0; c0 < d.n; c0 += 16) {
+    const int rc = min(16, d.n - c0);
+    if (rc == 1) trsm_l_pass<TL, 1>(d, lds, c0, rc);
+    else if (rc <= 4) trsm_l_pass<TL, 4>(d, lds, c0, rc);
+    else trsm_l_pass<TL, 16>(d, lds, c0, rc);
   }
 }
 
 // B (nb x r) <- L^{-T} B: blocks from the bottom; the contribution of later
-// rows uses columns of L (row p of L gives L^T's column p).
-template <typename TL>
-__device__ __forceinline__ void run_trsm_lt(const TaskDesc &d, double *lds) {
+// rows p to row i uses L[p][i] (16 lanes read 16 consecutive entries of a
+// row of L).
+template <typename TL, int CW>
+__device__ __forceinline__ void trsm_lt_pass(const TaskDesc &d, double *lds, int c0, int rc) {
   const gptr<const TL> L = (const gptr<const TL>)d.a;
   const int64_t ldl = d.lda;
   gdouble *Bm = (gdouble *)d.c;
   const int64_t ldb = d.ldc;
-  const int nb = d.m, r = d.n;
+  const int nb = d.m;
   const int tid = threadIdx.x;
-  double *part = lds;
-  double *red = lds + 16 * 16 * 16;
+  const int nb16 = (nb + 15) / 16 * 16;
+  double *Bs = lds;
+  double *part = Bs + nb16 * BSS;
+  double *Ljj = part + 16 * 16 * 16 + 16 * 16;
+  const int ci = tid & 15, sl = tid >> 4;
   const int nblk = (nb + 15) / 16;
-  for (int c0 = 0; c0 < r; c0 += 16) {
-    const int rc = min(16, r - c0);
-    for (int bi = nblk - 1; bi >= 0; --bi) {
-      const int i0 = 16 * bi;
-      const int h = min(16, nb - i0);
-      {
-        const int ci = tid & 15, sl = tid >> 4;   // output row i0+ci, slice sl
-        double acc[16];
+  solve_stage<CW>(Bs, Bm, ldb, nb, nb16, c0, rc);
+  __syncthreads();
+  for (int bi = nblk - 1; bi >= 0; --bi) {
+    const int i0 = 16 * bi;
+    const int h = min(16, nb - i0);
+    // later rows p = i0 + 16 + sl + 16 u, u < nu (uniform; rows past nb
+    // read as zero and meet zero rows of Bs)
+    const int nu = (nb16 - i0 - 16) / 16;
+    double acc[CW];
 #pragma unroll
-        for (int c = 0; c < 16; ++c) acc[c] = 0.0;
-        if (ci < h) {
-          for (int p = i0 + 16 + sl; p < nb; p += 16) {
-            const double lv = (double)L[(int64_t)p * ldl + i0 + ci];
-            const gdouble *bp = Bm + (int64_t)p * ldb + c0;
+    for (int c = 0; c < CW; ++c) acc[c] = 0.0;
+    if (ci < h) {
+      double lv[MAX_TILE / 16];
 #pragma unroll
-            for (int c = 0; c < 16; ++c)
-              if (c < rc) acc[c] += lv * bp[c];
-          }
-        }
-#pragma unroll
-        for (int c = 0; c < 16; ++c) part[(ci * 16 + sl) * 16 + c] = acc[c];
+      for (int u = 0; u < MAX_TILE / 16; ++u) {
+        const int p = i0 + 16 + sl + 16 * u;
+        lv[u] = (u < nu && p < nb) ? (double)L[(int64_t)p * ldl + i0 + ci] : 0.0;
       }
-      __syncthreads();
-      {
-        const int ri = tid >> 4, c = tid & 15;
-        double s = 0.0;
-        for (int sl = 0; sl < 16; ++sl) s += part[(ri * 16 + sl) * 16 + c];
-        red[ri * 16 + c] = s;
-      }
-      __syncthreads();
-      if (tid < rc) {
-        const int c = tid;
-        double x[16];
 #pragma unroll
-        for (int ii = 15; ii >= 0; --ii) {
-          if (ii < h) {
-            double t = Bm[(int64_t)(i0 + ii) * ldb + c0 + c] - red[ii * 16 + c];
+      for (int u = 0; u < MAX_TILE / 16; ++u) {
+        if (u < nu) {
 #pragma unroll
-            for (int p = 15; p > ii; --p)
-              if (p < h) t = t - (double)L[(int64_t)(i0 + p) * ldl + i0 + ii] * x[p];
-            x[ii] = t / (double)L[(int64_t)(i0 + ii) * ldl + i0 + ii];
-            Bm[(int64_t)(i0 + ii) * ldb + c0 + c] = x[ii];
-          }
+          for (int c = 0; c < CW; ++c) acc[c] += lv[u] * Bs[(i0 + 16 + sl + 16 * u) * BSS + c];
         }
       }
-      __syncthreads();
     }
+    // diagonal block, row sl of it: L[i0 + sl][i0 + ci]
+    Ljj[sl * 17 + ci] =
+        (sl < h && ci <= sl) ? (double)L[(int64_t)(i0 + sl) * ldl + i0 + ci] : 0.0;
+#pragma unroll
+    for (int c = 0; c < CW; ++c) part[(ci * 16 + sl) * 16 + c] = acc[c];
+    __syncthreads();
+    solve_block<false>(Bs, part, Ljj, i0, h, rc);
+    __syncthreads();
+  }
+  for (int idx = tid; idx < nb * CW; idx += NT) {
+    const int i = idx / CW, c = idx % CW;
+    if (c < rc) Bm[(int64_t)i * ldb + c0 + c] = Bs[i * BSS + c];
+  }
+  __syncthreads();
+}
+
+template <typename TL>
+__device__ __forceinline__ void run_trsm_lt(const TaskDesc &d, double *lds) {
+  for (int c0 = 0; c0 < d.n; c0 += 16) {
+    const int rc = min(16, d.n - c0);
+    if (rc == 1) trsm_lt_pass<TL, 1>(d, lds, c0, rc);
+    else if (rc <= 4) trsm_lt_pass<TL, 4>(d, lds, c0, rc);
+    else trsm_lt_pass<TL, 16>(d, lds, c0, rc);
   }
 }
 
-// B_I (m x r) -= L_IK (m x kb) Y_K (kb x r); unit = 64 rows; each wave takes
-// 16 rows, lanes split the kb sum, a fixed butterfly reduces across lanes.
+// B_I (m x r) -= L_IK (m x kb) Y_K (kb x r); unit = 16 rows, thread (row,
+// slice) sums every 16th term with eight loads in flight; fixed-order
+// reduction over the slices in LDS.
 template <typename TL>
-__device__ __forceinline__ void run_gemm_rhs_n(const TaskDesc &d, int unit) {
+__device__ __forceinline__ void run_gemm_rhs_n(const TaskDesc &d, int unit, double *lds) {
   const gptr<const TL> L = (const gptr<const TL>)d.a;
   const gdouble *Y = (const gdouble *)d.b;
   gdouble *Bm = (gdouble *)d.c;
   const int m = d.m, r = d.n, kb = d.k;
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int i0 = unit * ROW_UNIT;
-  for (int ii = w; ii < ROW_UNIT; ii += 4) {
-    const int i = i0 + ii;
-    if (i >= m) break;
-    gptr<const TL> lr = L + (int64_t)i * d.lda;
-    for (int c0 = 0; c0 < r; c0 += 8) {
-      double acc[8];
+  const int tid = threadIdx.x;
+  const int ri = tid >> 4, sl = tid & 15;
+  const int i0 = unit * RHS_ROWS;
+  const int i = i0 + ri;
+  double *part = lds;   // [16 rows][16 slices][8 cols]
+  for (int c0 = 0; c0 < r; c0 += 8) {
+    double acc[8];
 #pragma unroll
-      for (int c = 0; c < 8; ++c) acc[c] = 0.0;
-      for (int p = lane; p < kb; p += 64) {
-        const double lv = (double)lr[p];
-        const gdouble *yp = Y + (int64_t)p * d.ldb + c0;
+    for (int c = 0; c < 8; ++c) acc[c] = 0.0;
+    if (i < m) {
+      gptr<const TL> lr = L + (int64_t)i * d.lda;
+      for (int pb = 0; pb < kb; pb += 128) {
+        double lv[8];
 #pragma unroll
-        for (int c = 0; c < 8; ++c)
-          if (c0 + c < r) acc[c] += lv * yp[c];
-      }
+        for (int u = 0; u < 8; ++u) {
+          const int p = pb + sl + 16 * u;
+          lv[u] = p < kb ? (double)lr[p] : 0.0;
+        }
 #pragma unroll
-      for (int c = 0; c < 8; ++c) {
-        double v = acc[c];
+        for (int u = 0; u < 8; ++u) {
+          const int p = pb + sl + 16 * u;
+          if (p < kb) {
+            const gdouble *yp = Y + (int64_t)p * d.ldb + c0;
 #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-        acc[c] = v;
-      }
-      if (lane < 8 && c0 + lane < r) {
-        double v = acc[0];
-#pragma unroll
-        for (int c = 1; c < 8; ++c)
-          if (lane == c) v = acc[c];
-        gdouble *bp = Bm + (int64_t)i * d.ldc + c0 + lane;
-        *bp = *bp - v;
+            for (int c = 0; c < 8; ++c)
+              if (c0 + c < r) acc[c] += lv[u] * yp[c];
+          }
+        }
       }
     }
+#pragma unroll
+    for (int c = 0; c < 8; ++c) part[(ri * 16 + sl) * 8 + c] = acc[c];
+    __syncthreads();
+    if (sl < 8 && i < m && c0 + sl < r) {
+      double sum = 0.0;
+#pragma unroll
+      for (int q = 0; q < 16; ++q) sum += part[(ri * 16 + q) * 8 + sl];
+      gdouble *bp = Bm + (int64_t)i * d.ldc + c0 + sl;
+      *bp = *bp - sum;
+    }
+    __syncthreads();
   }
 }
 
-// B_I (m x r) -= L_KI^T Y_K with L_KI (kb x m); unit = 64 output rows, four
-// slices of the kb sum per row, summed in a fixed order.
+// B_I (m x r) -= L_KI^T Y_K with L_KI (kb x m); unit = 16 output rows,
+// thread (row, slice) reads L_KI[p][i] (16 consecutive entries of row p per
+// 16 lanes); fixed-order reduction over the slices.
 template <typename TL>
 __device__ __forceinline__ void run_gemm_rhs_t(const TaskDesc &d, int unit, double *lds) {
   const gptr<const TL> L = (const gptr<const TL>)d.a;
@@ -533,34 +613,46 @@ __device__ __forceinline__ void run_gemm_rhs_t(const TaskDesc &d, int unit, doub
   gdouble *Bm = (gdouble *)d.c;
   const int m = d.m, r = d.n, kb = d.k;
   const int tid = threadIdx.x;
-  const int ii = tid & 63, sl = tid >> 6;
-  const int i = unit * ROW_UNIT + ii;
-  double *part = lds;   // [4][64][8]
+  const int ci = tid & 15, sl = tid >> 4;
+  const int i0 = unit * RHS_ROWS;
+  const int i = i0 + ci;
+  double *part = lds;   // [16 rows][16 slices][8 cols]
   for (int c0 = 0; c0 < r; c0 += 8) {
     double acc[8];
 #pragma unroll
     for (int c = 0; c < 8; ++c) acc[c] = 0.0;
     if (i < m) {
-      for (int p = sl; p < kb; p += 4) {
-        const double lv = (double)L[(int64_t)p * d.lda + i];
-        const gdouble *yp = Y + (int64_t)p * d.ldb + c0;
+      for (int pb = 0; pb < kb; pb += 128) {
+        double lv[8];
 #pragma unroll
-        for (int c = 0; c < 8; ++c)
-          if (c0 + c < r) acc[c] += lv * yp[c];
+        for (int u = 0; u < 8; ++u) {
+          const int p = pb + sl + 16 * u;
+          lv[u] = p < kb ? (double)L[(int64_t)p * d.lda + i] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int p = pb + sl + 16 * u;
+          if (p < kb) {
+            const gdouble *yp = Y + (int64_t)p * d.ldb + c0;
+#pragma unroll
+            for (int c = 0; c < 8; ++c)
+              if (c0 + c < r) acc[c] += lv[u] * yp[c];
+          }
+        }
       }
     }
 #pragma unroll
-    for (int c = 0; c < 8; ++c) part[(sl * 64 + ii) * 8 + c] = acc[c];
+    for (int c = 0; c < 8; ++c) part[(ci * 16 + sl) * 8 + c] = acc[c];
     __syncthreads();
-    if (sl == 0 && i < m) {
+    {
+      const int ro = tid >> 4, c = tid & 15;   // output row ro, column c
+      const int io = i0 + ro;
+      if (c < 8 && io < m && c0 + c < r) {
+        double sum = 0.0;
 #pragma unroll
-      for (int c = 0; c < 8; ++c) {
-        if (c0 + c < r) {
-          const double s = ((part[(0 * 64 + ii) * 8 + c] + part[(1 * 64 + ii) * 8 + c]) +
-                            part[(2 * 64 + ii) * 8 + c]) + part[(3 * 64 + ii) * 8 + c];
-          gdouble *bp = Bm + (int64_t)i * d.ldc + c0 + c;
-          *bp = *bp - s;
-        }
+        for (int q = 0; q < 16; ++q) sum += part[(ro * 16 + q) * 8 + c];
+        gdouble *bp = Bm + (int64_t)io * d.ldc + c0 + c;
+        *bp = *bp - sum;
       }
     }
     __syncthreads();
@@ -793,7 +885,7 @@ __global__ void __launch_bounds__(NT, 1) dc_level_kernel(LevelArgs A) {
           if (d.ta == T_F32) run_trsm_lt<float>(d, lds); else run_trsm_lt<double>(d, lds);
           break;
         case K_GEMM_RHS_N:
-          if (d.ta == T_F32) run_gemm_rhs_n<float>(d, u); else run_gemm_rhs_n<double>(d, u);
+          if (d.ta == T_F32) run_gemm_rhs_n<float>(d, u, lds); else run_gemm_rhs_n<double>(d, u, lds);
           break;
         case K_GEMM_RHS_T:
           if (d.ta == T_F32) run_gemm_rhs_t<float>(d, u, lds); else run_gemm_rhs_t<double>(d, u, lds);

@@ -42,6 +42,17 @@ __host__ __device__ inline int trsm_lds_doubles(int nb) {
 __host__ __device__ inline int potrf_lds_doubles(int nb) {
   return PANEL * panel_stride(nb) + PANEL * (PANEL + 1) + 8;
 }
+// Solve units (TRSM_L, TRSM_LT): the right-hand-side columns of the tile
+// (nb x 16, row stride BSS: 16 lanes reading one column of 16 different rows
+// hit distinct banks), partial sums [16 rows][16 slices][16 cols], their
+// reduction [16][16] and the 16x16 diagonal block of L.
+constexpr int BSS = 17;
+__host__ __device__ constexpr int solve_lds_doubles(int nb) {
+  return (nb + 15) / 16 * 16 * BSS + 16 * 16 * 16 + 16 * 16 + 16 * 17;
+}
+// Rows of a right-hand-side update unit (GEMM_RHS_N, GEMM_RHS_T) and its LDS.
+constexpr int RHS_ROWS = 16;
+constexpr int RHS_LDS_DOUBLES = 16 * 16 * 8;
 constexpr int PANEL_LDS_DOUBLES = 2 * TRSM_ROWS * (MAX_TILE + 2) + PANEL * (PANEL + 1);
 
 // One task, as the executor reads it (128 bytes).

@@ -358,7 +358,8 @@ static int units_for(const TaskDesc &d) {
     case K_GEMM: return std::max(1, cdiv(d.m, GEMM_UNIT) * cdiv(d.n, GEMM_UNIT));
     case K_SYRK: { int p = cdiv(d.m, GEMM_UNIT); return std::max(1, p * (p + 1) / 2); }
     case K_TRSM: case K_TRSM_CAST: return std::max(1, cdiv(d.m, trsm_rows(d.n)));
-    case K_GEMM_RHS_N: case K_GEMM_RHS_T: case K_CAST: case K_RESID: case K_AXPY:
+    case K_GEMM_RHS_N: case K_GEMM_RHS_T: return std::max(1, cdiv(d.m, RHS_ROWS));
+    case K_CAST: case K_RESID: case K_AXPY:
       return std::max(1, cdiv(d.m, ROW_UNIT));
     case K_SCAL: return std::max(1, cdiv(d.m, 4096));
     default: return 1;
@@ -692,8 +693,8 @@ static size_t lds_for(const TaskDesc &d) {
   switch (d.kind) {
     case K_TRSM: case K_TRSM_CAST: return (size_t)trsm_lds_doubles(d.n) * 8;
     case K_POTRF: return (size_t)potrf_lds_doubles(d.m) * 8;
-    case K_TRSM_L: case K_TRSM_LT: return (size_t)(16 * 16 * 16 + 16 * 16) * 8;
-    case K_GEMM_RHS_T: return (size_t)(4 * 64 * 8) * 8;
+    case K_TRSM_L: case K_TRSM_LT: return (size_t)solve_lds_doubles(d.m) * 8;
+    case K_GEMM_RHS_N: case K_GEMM_RHS_T: return (size_t)RHS_LDS_DOUBLES * 8;
     case K_RESID: return (size_t)(2 * 64 * 8 + 4 * 64 * 8) * 8;
     default: return 16;
   }
