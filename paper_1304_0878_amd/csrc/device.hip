@@ -386,6 +386,14 @@ __device__ __forceinline__ void solve_stage(double *Bs, const gdouble *Bm, int64
 // row at a time, x_i = t_i * (1 / l_ii) on lane i shared across its column
 // group, the other rows dropping their terms in x_i.  FORWARD: rows top down,
 // lrow[i] = l_qi; otherwise bottom up with lrow[i] = l_iq.
+// Value of v on lane `lane` (a constant), in every lane.
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffff), lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 template <bool FORWARD>
 __device__ __forceinline__ void solve_block(double *Bs, const double *part, const double *Ljj,
                                             int i0, int h, int rc) {
@@ -410,7 +418,13 @@ __device__ __forceinline__ void solve_block(double *Bs, const double *part, cons
       const int i = FORWARD ? k : 15 - k;
       if (i < h) {
         if (q == i) t = t * rinv;
-        const double xi = __shfl(t, (g << 4) + i);
+        // x_i of each column group: lanes i, 16 + i, 32 + i, 48 + i
+        double xi = readlane_f64(t, i);
+        if (rc > 1) {
+          const double x1 = readlane_f64(t, 16 + i), x2 = readlane_f64(t, 32 + i),
+                       x3 = readlane_f64(t, 48 + i);
+          xi = g == 1 ? x1 : g == 2 ? x2 : g == 3 ? x3 : xi;
+        }
         if (FORWARD ? q > i : q < i) t = t - lrow[i] * xi;
       }
     }
@@ -436,6 +450,20 @@ __device__ __forceinline__ void trsm_l_pass(const TaskDesc &d, double *lds, int 
   double *Ljj = part + 16 * 16 * 16 + 16 * 16;     // [16][17]
   const int ri = tid >> 4, sl = tid & 15;
   solve_stage<CW>(Bs, Bm, ldb, nb, nb16, c0, rc);
+  // this thread's entries of L for a block at row i0: row i0 + ri, columns
+  // sl + 16 u left of the block and the diagonal one; those of the next
+  // block are loaded while the current block is being solved
+  double lv[MAX_TILE / 16];
+  double ldg = 0.0;
+  auto lload = [&](int i0) {
+    const int h = min(16, nb - i0), nu = i0 / 16;
+    gptr<const TL> lr = L + (int64_t)(i0 + ri) * ldl;
+#pragma unroll
+    for (int u = 0; u < MAX_TILE / 16; ++u)
+      lv[u] = (ri < h && u < nu) ? (double)lr[sl + 16 * u] : 0.0;
+    ldg = (ri < h && sl <= ri) ? (double)lr[i0 + sl] : 0.0;
+  };
+  lload(0);
   __syncthreads();
   for (int i0 = 0; i0 < nb; i0 += 16) {
     const int h = min(16, nb - i0);
@@ -444,11 +472,6 @@ __device__ __forceinline__ void trsm_l_pass(const TaskDesc &d, double *lds, int 
 #pragma unroll
     for (int c = 0; c < CW; ++c) acc[c] = 0.0;
     if (ri < h) {
-      gptr<const TL> lr = L + (int64_t)(i0 + ri) * ldl;
-      double lv[MAX_TILE / 16];
-#pragma unroll
-      for (int u = 0; u < MAX_TILE / 16; ++u) lv[u] = u < nu ? (double)lr[sl + 16 * u] : 0.0;
-      const double ldg = sl <= ri ? (double)lr[i0 + sl] : 0.0;
 #pragma unroll
       for (int u = 0; u < MAX_TILE / 16; ++u) {
         if (u < nu) {
@@ -460,6 +483,7 @@ __device__ __forceinline__ void trsm_l_pass(const TaskDesc &d, double *lds, int 
     }
 #pragma unroll
     for (int c = 0; c < CW; ++c) part[(ri * 16 + sl) * 16 + c] = acc[c];
+    if (i0 + 16 < nb) lload(i0 + 16);
     __syncthreads();
     solve_block<true>(Bs, part, Ljj, i0, h, rc);
     __syncthreads();
@@ -499,23 +523,31 @@ __device__ __forceinline__ void trsm_lt_pass(const TaskDesc &d, double *lds, int
   const int ci = tid & 15, sl = tid >> 4;
   const int nblk = (nb + 15) / 16;
   solve_stage<CW>(Bs, Bm, ldb, nb, nb16, c0, rc);
+  // this thread's entries of L for the block at row i0: column i0 + ci of
+  // the later rows p = i0 + 16 + sl + 16 u (u < nu, uniform; rows past nb
+  // read as zero and meet zero rows of Bs) and of the diagonal block; those
+  // of the next block up are loaded while the current one is being solved
+  double lv[MAX_TILE / 16];
+  double ldg = 0.0;
+  auto lload = [&](int i0) {
+    const int h = min(16, nb - i0), nu = (nb16 - i0 - 16) / 16;
+#pragma unroll
+    for (int u = 0; u < MAX_TILE / 16; ++u) {
+      const int p = i0 + 16 + sl + 16 * u;
+      lv[u] = (ci < h && u < nu && p < nb) ? (double)L[(int64_t)p * ldl + i0 + ci] : 0.0;
+    }
+    ldg = (sl < h && ci <= sl) ? (double)L[(int64_t)(i0 + sl) * ldl + i0 + ci] : 0.0;
+  };
+  lload(16 * (nblk - 1));
   __syncthreads();
   for (int bi = nblk - 1; bi >= 0; --bi) {
     const int i0 = 16 * bi;
     const int h = min(16, nb - i0);
-    // later rows p = i0 + 16 + sl + 16 u, u < nu (uniform; rows past nb
-    // read as zero and meet zero rows of Bs)
     const int nu = (nb16 - i0 - 16) / 16;
     double acc[CW];
 #pragma unroll
     for (int c = 0; c < CW; ++c) acc[c] = 0.0;
     if (ci < h) {
-      double lv[MAX_TILE / 16];
-#pragma unroll
-      for (int u = 0; u < MAX_TILE / 16; ++u) {
-        const int p = i0 + 16 + sl + 16 * u;
-        lv[u] = (u < nu && p < nb) ? (double)L[(int64_t)p * ldl + i0 + ci] : 0.0;
-      }
 #pragma unroll
       for (int u = 0; u < MAX_TILE / 16; ++u) {
         if (u < nu) {
@@ -525,10 +557,10 @@ __device__ __forceinline__ void trsm_lt_pass(const TaskDesc &d, double *lds, int
       }
     }
     // diagonal block, row sl of it: L[i0 + sl][i0 + ci]
-    Ljj[sl * 17 + ci] =
-        (sl < h && ci <= sl) ? (double)L[(int64_t)(i0 + sl) * ldl + i0 + ci] : 0.0;
+    Ljj[sl * 17 + ci] = ldg;
 #pragma unroll
     for (int c = 0; c < CW; ++c) part[(ci * 16 + sl) * 16 + c] = acc[c];
+    if (bi > 0) lload(i0 - 16);
     __syncthreads();
     solve_block<false>(Bs, part, Ljj, i0, h, rc);
     __syncthreads();
