@@ -134,8 +134,13 @@ int dc_shutdown(dc_runtime *rt);
 int dc_vector_register(dc_runtime *rt, dc_handle *out, void *ptr, int64_t nx,
                        dc_dtype dtype);
 
-/* Registers a rows x cols row-major matrix with leading dimension ld >= cols
- * (Section 5.1's matrix).  Errors: -EINVAL, -EBUSY. */
+/* Largest accepted leading dimension, in elements.  The GEMM kernels address
+ * the rows of one 128-row unit through a 32-bit byte offset, which this bound
+ * keeps below 2 GiB (a square FP64 matrix of this order would need 32 TiB). */
+#define DC_MAX_LD ((int64_t)1 << 21)
+
+/* Registers a rows x cols row-major matrix with leading dimension
+ * cols <= ld <= DC_MAX_LD (Section 5.1's matrix).  Errors: -EINVAL, -EBUSY. */
 int dc_matrix_register(dc_runtime *rt, dc_handle *out, void *ptr, int64_t rows,
                        int64_t cols, int64_t ld, dc_dtype dtype);
 

@@ -92,9 +92,11 @@ extern "C++" int dcx_launch_level(const dcx::LevelArgs &args, int workers, size_
                                   void *stream);
 // Allows the level kernel its largest dynamic LDS size.
 extern "C++" int dcx_level_setup(void);
-// Launches the GEMM/SYRK kernel of one level on `stream`.
+// Launches the FP64 GEMM/SYRK kernel of one level on `stream`.
 extern "C++" int dcx_launch_gemm(const dcx::LevelArgs &args, int workers, void *stream);
-// Allows the GEMM/SYRK kernel its dynamic LDS size.
+// Launches the GEMM/SYRK kernel for FP32/BF16 inputs of one level on `stream`.
+extern "C++" int dcx_launch_gemm_lowp(const dcx::LevelArgs &args, int workers, void *stream);
+// Allows the GEMM/SYRK kernels their dynamic LDS sizes.
 extern "C++" int dcx_gemm_setup(void);
 // Workgroups per CU the level kernel keeps resident with lds_bytes of LDS.
 extern "C++" int dcx_level_occupancy(size_t lds_bytes, int *blocks_per_cu);

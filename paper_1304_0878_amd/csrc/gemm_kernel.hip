@@ -36,55 +36,114 @@ typedef __attribute__((address_space(1))) fvec4 gfvec4;
 typedef __attribute__((address_space(1))) bvec8 gbvec8;
 template <typename T> using gp = __attribute__((address_space(1))) T *;
 
-__device__ __forceinline__ double mfma44(double a, double b, double c) {
-  return __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, c, 0, 0, 0);
-}
-
 // ------------------------------------------------------------------ FP64
+//
+// FP64 units run in their own kernel: 256 threads (four waves in a 2 x 2
+// grid of 64 x 64 tiles), two workgroups per CU, 16x16x4 FP64 MFMA (lane l
+// supplies A[l%16][l/16] and B^T[l/16][l%16]; result element e of lane l is
+// D[l/16 + 4e][l%16]).  K chunks of 16 are staged in LDS, double buffered,
+// with an odd row stride (17 doubles): the 16 lanes that read one fragment
+// at a time read 16 rows at one column, which then fall in distinct banks.
+// C is pre-loaded negated into the accumulators, so the epilogue is a plain
+// store of the negation.
 
-constexpr int KC64 = 32;
-constexpr int S64 = KC64 + 2;                 // doubles per LDS row
+constexpr int GT64 = 256;
+constexpr int KC64 = 16;
+constexpr int S64 = KC64 + 1;                 // doubles per LDS row
 constexpr int STAGE64 = 2 * GEMM_UNIT * S64;  // A and B of one stage
 
-__device__ __forceinline__ void block_f64(gdouble *__restrict__ C, int64_t ldc,
-                                          const gdouble *__restrict__ A, int64_t lda,
-                                          const gdouble *__restrict__ B, int64_t ldb, int M,
-                                          int N, int K, bool lower_only, double *lds) {
+typedef double dvec4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ dvec4 mfma16(double a, double b, dvec4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// Global memory is reached through buffer resources that span exactly the
+// unit's rows of each operand: a per-lane 32-bit offset plus a wave-uniform
+// scalar offset per row group, so addressing costs one VGPR per operand, and
+// an access outside the span reads zero or is dropped instead of faulting.
+// The row span of one unit is below 4 GiB because leading dimensions are
+// limited at registration.
+__device__ __forceinline__ uint64_t uniform_u64(uint64_t v) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t span_rsrc(const void *base, int64_t rows,
+                                                            int64_t ld, int64_t cols) {
+  const int64_t bytes = rows > 0 ? ((rows - 1) * ld + cols) * 8 : 0;
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), 0, (int)(uint32_t)bytes,
+                                           0x00020000);
+}
+__device__ __forceinline__ double bload(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+__device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff,
+                                       double v) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, 0);
+}
+
+// Ragged units (M or N below the unit size, K not a multiple of the chunk)
+// clamp row and column indices, so every load stays inside the unit: rows
+// past M (N) only feed output rows (columns) that are not stored, and
+// columns past K are selected to zero.  dlim is the largest column - row
+// offset that is stored: 0 for the lower-triangular diagonal units of SYRK,
+// otherwise unbounded.  It depends on the unit, so the comparison stays
+// inside the unit loop instead of being hoisted into 64 saved masks.
+template <bool FULL>
+__device__ __forceinline__ void block_f64(void *C, int64_t ldc, const void *A, int64_t lda,
+                                          const void *B, int64_t ldb, int M, int N, int K,
+                                          int dlim, double *lds) {
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int wr = w >> 2, wc = w & 3;
-  const int l16 = lane & 15, blk = l16 >> 2, kq = lane >> 4, n4 = lane & 3;
-  double acc[4][2][4];
+  const int wr = w >> 1, wc = w & 1;
+  const int l16 = lane & 15, kq = lane >> 4;
+  const int r0 = 64 * wr + kq, c0 = 64 * wc + l16;  // element (i, j, e) at r0 + 16i + 4e, c0 + 16j
+  const __amdgpu_buffer_rsrc_t rc = span_rsrc(C, M, ldc, N);
+  const __amdgpu_buffer_rsrc_t ra_ = span_rsrc(A, M, lda, K);
+  const __amdgpu_buffer_rsrc_t rb_ = span_rsrc(B, N, ldb, K);
+  const uint32_t cld = (uint32_t)ldc * 8;
+  dvec4 acc[4][4];
+  {
+    const uint32_t cv = FULL ? ((uint32_t)r0 * (uint32_t)ldc + c0) * 8 : 0;
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int c = 0; c < 2; ++c)
+      for (int j = 0; j < 4; ++j)
 #pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        const int row = 64 * wr + 16 * i + 4 * blk + kq;
-        const int col = 32 * wc + 16 * c + 4 * ((blk + s) & 3) + n4;
-        const bool ok = row < M && col < N && (!lower_only || col <= row);
-        acc[i][c][s] = ok ? -C[(int64_t)row * ldc + col] : 0.0;
-      }
-  // loader: 16 threads per row (16-byte pairs), 32 rows per pass, 4 passes
-  const int lrow = tid >> 4, lkp = (tid & 15) * 2;
-  const bool fast = M == GEMM_UNIT && N == GEMM_UNIT && (K % KC64) == 0 &&
-                    (((uintptr_t)A | (uintptr_t)B) & 15) == 0 && ((lda | ldb) & 1) == 0;
-  dvec2 ra[4], rb[4];
+        for (int e = 0; e < 4; ++e) {
+          if (FULL) {
+            acc[i][j][e] = -bload(rc, cv + 128 * j, (16 * i + 4 * e) * cld);
+          } else {
+            const uint32_t row = min(r0 + 16 * i + 4 * e, M - 1);
+            const uint32_t col = min(c0 + 16 * j, N - 1);
+            acc[i][j][e] = -bload(rc, (row * (uint32_t)ldc + col) * 8, 0);
+          }
+        }
+  }
+  // loader: thread -> rows tid/16 + 16 jj, column tid%16 of the chunk
+  const int lrow = tid >> 4, lcol = tid & 15;
+  const uint32_t ald = (uint32_t)lda * 8, bld = (uint32_t)ldb * 8;
+  const uint32_t av = (uint32_t)lrow * ald + lcol * 8, bv = (uint32_t)lrow * bld + lcol * 8;
+  double ra[8], rb[8];
   auto gload = [&](int k0) {
+    if (FULL) {
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int row = lrow + 32 * j;
-      if (fast) {
-        ra[j] = *(const gdvec2 *)(A + (int64_t)row * lda + k0 + lkp);
-        rb[j] = *(const gdvec2 *)(B + (int64_t)row * ldb + k0 + lkp);
-      } else {
-        const int k = k0 + lkp;
-        const gdouble *ap = A + (int64_t)row * lda + k;
-        const gdouble *bp = B + (int64_t)row * ldb + k;
-        ra[j].x = (row < M && k < K) ? ap[0] : 0.0;
-        ra[j].y = (row < M && k + 1 < K) ? ap[1] : 0.0;
-        rb[j].x = (row < N && k < K) ? bp[0] : 0.0;
-        rb[j].y = (row < N && k + 1 < K) ? bp[1] : 0.0;
+      for (int jj = 0; jj < 8; ++jj) {
+        ra[jj] = bload(ra_, av, 16 * jj * ald + k0 * 8);
+        rb[jj] = bload(rb_, bv, 16 * jj * bld + k0 * 8);
+      }
+    } else {
+      const uint32_t kc = min(k0 + lcol, K - 1);
+#pragma unroll
+      for (int jj = 0; jj < 8; ++jj) {
+        const uint32_t ar = min(lrow + 16 * jj, M - 1), br = min(lrow + 16 * jj, N - 1);
+        ra[jj] = bload(ra_, (ar * (uint32_t)lda + kc) * 8, 0);
+        rb[jj] = bload(rb_, (br * (uint32_t)ldb + kc) * 8, 0);
+      }
+      if (k0 + lcol >= K) {
+#pragma unroll
+        for (int jj = 0; jj < 8; ++jj) ra[jj] = rb[jj] = 0.0;
       }
     }
   };
@@ -92,9 +151,9 @@ __device__ __forceinline__ void block_f64(gdouble *__restrict__ C, int64_t ldc,
     double *As = lds + st * STAGE64;
     double *Bs = As + GEMM_UNIT * S64;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      *(dvec2 *)(As + (lrow + 32 * j) * S64 + lkp) = ra[j];
-      *(dvec2 *)(Bs + (lrow + 32 * j) * S64 + lkp) = rb[j];
+    for (int jj = 0; jj < 8; ++jj) {
+      As[(lrow + 16 * jj) * S64 + lcol] = ra[jj];
+      Bs[(lrow + 16 * jj) * S64 + lcol] = rb[jj];
     }
   };
   const int nst = (K + KC64 - 1) / KC64;
@@ -109,34 +168,30 @@ __device__ __forceinline__ void block_f64(gdouble *__restrict__ C, int64_t ldc,
 #pragma unroll
     for (int ks = 0; ks < KC64 / 4; ++ks) {
       const int kk = 4 * ks + kq;
-      double a[4], b[2][4];
+      double a[4], b[4];
 #pragma unroll
       for (int i = 0; i < 4; ++i) a[i] = As[(64 * wr + 16 * i + l16) * S64 + kk];
 #pragma unroll
-      for (int c = 0; c < 2; ++c)
-#pragma unroll
-        for (int s = 0; s < 4; ++s)
-          b[c][s] = Bs[(32 * wc + 16 * c + 4 * ((blk + s) & 3) + n4) * S64 + kk];
+      for (int j = 0; j < 4; ++j) b[j] = Bs[(64 * wc + 16 * j + l16) * S64 + kk];
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int c = 0; c < 2; ++c)
-#pragma unroll
-          for (int s = 0; s < 4; ++s) acc[i][c][s] = mfma44(a[i], b[c][s], acc[i][c][s]);
+        for (int j = 0; j < 4; ++j) acc[i][j] = mfma16(a[i], b[j], acc[i][j]);
     }
     if (st + 1 < nst) sstore(cur ^ 1);
     __syncthreads();
   }
+  const int dbase = c0 - r0;
+  const uint32_t cv = ((uint32_t)r0 * (uint32_t)ldc + c0) * 8;
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int c = 0; c < 2; ++c)
+    for (int j = 0; j < 4; ++j)
 #pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        const int row = 64 * wr + 16 * i + 4 * blk + kq;
-        const int col = 32 * wc + 16 * c + 4 * ((blk + s) & 3) + n4;
-        if (row < M && col < N && (!lower_only || col <= row))
-          C[(int64_t)row * ldc + col] = -acc[i][c][s];
+      for (int e = 0; e < 4; ++e) {
+        const int row = r0 + 16 * i + 4 * e, col = c0 + 16 * j;
+        if ((FULL || (row < M && col < N)) && dbase + 16 * (j - i) - 4 * e <= dlim)
+          bstore(rc, cv + 128 * j, (16 * i + 4 * e) * cld, -acc[i][j][e]);
       }
 }
 
@@ -321,62 +376,89 @@ __device__ __forceinline__ void block_bf16(gp<TOUT> __restrict__ C, int64_t ldc,
 
 // --------------------------------------------------------- unit dispatch
 
-__device__ __forceinline__ void run_unit(const TaskDesc &d, int unit, double *lds) {
-  int p, q;
-  bool lower_only;
+// Position of a unit in its task: the output block (p, q) of 128 x 128, its
+// extent, and for SYRK whether it lies on the diagonal (lower half only).
+struct UnitBlock {
   int M, N;
+  bool lower_only;
+  const void *a, *b;
+  int64_t lda, ldb, coff;
+};
+
+__device__ __forceinline__ UnitBlock unit_block(const TaskDesc &d, int unit, int esize) {
+  int p, q;
+  UnitBlock u;
   if (d.kind == K_SYRK) {
     p = 0;
     while ((p + 1) * (p + 2) / 2 <= unit) ++p;
     q = unit - p * (p + 1) / 2;
-    M = min(GEMM_UNIT, d.m - p * GEMM_UNIT);
-    N = min(GEMM_UNIT, d.m - q * GEMM_UNIT);
-    lower_only = p == q;
+    u.M = min(GEMM_UNIT, d.m - p * GEMM_UNIT);
+    u.N = min(GEMM_UNIT, d.m - q * GEMM_UNIT);
+    u.lower_only = p == q;
   } else {
     const int qn = (d.n + GEMM_UNIT - 1) / GEMM_UNIT;
     p = unit / qn;
     q = unit % qn;
-    M = min(GEMM_UNIT, d.m - p * GEMM_UNIT);
-    N = min(GEMM_UNIT, d.n - q * GEMM_UNIT);
-    lower_only = false;
+    u.M = min(GEMM_UNIT, d.m - p * GEMM_UNIT);
+    u.N = min(GEMM_UNIT, d.n - q * GEMM_UNIT);
+    u.lower_only = false;
   }
   const int r0 = p * GEMM_UNIT, c0 = q * GEMM_UNIT;
   // SYRK reads both operands from its one input
-  const void *bsrc = d.kind == K_SYRK ? d.a : d.b;
-  const int64_t ldb = d.kind == K_SYRK ? d.lda : d.ldb;
-  const int64_t coff = (int64_t)r0 * d.ldc + c0;
-  if (d.ta == T_F64) {
-    block_f64((gdouble *)d.c + coff, d.ldc, (const gdouble *)d.a + (int64_t)r0 * d.lda, d.lda,
-              (const gdouble *)bsrc + (int64_t)c0 * ldb, ldb, M, N, d.k, lower_only, lds);
-  } else if (d.ta == T_F32) {
-    const gfloat *A = (const gfloat *)d.a + (int64_t)r0 * d.lda;
-    const gfloat *B = (const gfloat *)bsrc + (int64_t)c0 * ldb;
+  u.lda = d.lda;
+  u.ldb = d.kind == K_SYRK ? d.lda : d.ldb;
+  u.a = (const char *)d.a + (int64_t)r0 * d.lda * esize;
+  u.b = (const char *)(d.kind == K_SYRK ? d.a : d.b) + (int64_t)c0 * u.ldb * esize;
+  u.coff = (int64_t)r0 * d.ldc + c0;
+  return u;
+}
+
+__device__ __forceinline__ void run_unit_f64(const TaskDesc &d, int unit, double *lds) {
+  const UnitBlock u = unit_block(d, unit, 8);
+  // buffer resources must sit in scalar registers: make the wave-uniform
+  // unit fields provably uniform so no per-lane resource loop is generated
+  auto su64 = [](const void *p) { return (void *)uniform_u64((uint64_t)p); };
+  auto s32 = [](int64_t v) { return (int64_t)(int)__builtin_amdgcn_readfirstlane((int)v); };
+  void *C = su64((double *)d.c + u.coff);
+  const void *a = su64(u.a), *b = su64(u.b);
+  const int64_t ldc = s32(d.ldc), lda = s32(u.lda), ldb = s32(u.ldb);
+  const int M = __builtin_amdgcn_readfirstlane(u.M), N = __builtin_amdgcn_readfirstlane(u.N);
+  const int K = __builtin_amdgcn_readfirstlane(d.k);
+  const int dlim = __builtin_amdgcn_readfirstlane(u.lower_only ? 0 : GEMM_UNIT);
+  if (M == GEMM_UNIT && N == GEMM_UNIT && K % KC64 == 0)
+    block_f64<true>(C, ldc, a, lda, b, ldb, M, N, K, dlim, lds);
+  else
+    block_f64<false>(C, ldc, a, lda, b, ldb, M, N, K, dlim, lds);
+}
+
+__device__ __forceinline__ void run_unit_lowp(const TaskDesc &d, int unit, double *lds) {
+  if (d.ta == T_F32) {
+    const UnitBlock u = unit_block(d, unit, 4);
+    const gfloat *A = (const gfloat *)u.a, *B = (const gfloat *)u.b;
     if (d.tc == T_F64)
-      block_f32<double>((gdouble *)d.c + coff, d.ldc, A, d.lda, B, ldb, M, N, d.k, lower_only,
-                         (float *)lds);
+      block_f32<double>((gdouble *)d.c + u.coff, d.ldc, A, u.lda, B, u.ldb, u.M, u.N, d.k,
+                         u.lower_only, (float *)lds);
     else
-      block_f32<float>((gfloat *)d.c + coff, d.ldc, A, d.lda, B, ldb, M, N, d.k, lower_only,
-                        (float *)lds);
+      block_f32<float>((gfloat *)d.c + u.coff, d.ldc, A, u.lda, B, u.ldb, u.M, u.N, d.k,
+                        u.lower_only, (float *)lds);
   } else {
-    const gbf16 *A = (const gbf16 *)d.a + (int64_t)r0 * d.lda;
-    const gbf16 *B = (const gbf16 *)bsrc + (int64_t)c0 * ldb;
+    const UnitBlock u = unit_block(d, unit, 2);
+    const gbf16 *A = (const gbf16 *)u.a, *B = (const gbf16 *)u.b;
     if (d.tc == T_F64)
-      block_bf16<double>((gdouble *)d.c + coff, d.ldc, A, d.lda, B, ldb, M, N, d.k, lower_only,
-                          (__bf16 *)lds);
+      block_bf16<double>((gdouble *)d.c + u.coff, d.ldc, A, u.lda, B, u.ldb, u.M, u.N, d.k,
+                          u.lower_only, (__bf16 *)lds);
     else
-      block_bf16<float>((gfloat *)d.c + coff, d.ldc, A, d.lda, B, ldb, M, N, d.k, lower_only,
-                         (__bf16 *)lds);
+      block_bf16<float>((gfloat *)d.c + u.coff, d.ldc, A, u.lda, B, u.ldb, u.M, u.N, d.k,
+                         u.lower_only, (__bf16 *)lds);
   }
 }
 
-__device__ __forceinline__ uint64_t uniform_u64(uint64_t v) {
-  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
-  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
-  return ((uint64_t)hi << 32) | lo;
-}
-
-__global__ void __launch_bounds__(GT, 1) dc_gemm_kernel(LevelArgs A) {
-  extern __shared__ double lds[];
+// Persistent loop of a GEMM kernel: take units from the level's counter
+// until the list is exhausted.  The failure flag of the unit's matrix can
+// be set during the level by a POTRF unit of the panel kernel, so one thread
+// reads it and the workgroup takes the decision from LDS after a barrier.
+template <typename RUN>
+__device__ __forceinline__ void unit_loop(const LevelArgs &A, double *lds, RUN run) {
   __shared__ uint64_t s_idx;
   __shared__ int s_skip;
   const int tid = threadIdx.x;
@@ -396,7 +478,7 @@ __global__ void __launch_bounds__(GT, 1) dc_gemm_kernel(LevelArgs A) {
         atomicMin((unsigned long long *)&A.trace[3 * t], (unsigned long long)wall_clock64());
     }
     __syncthreads();
-    if (!__builtin_amdgcn_readfirstlane(s_skip)) run_unit(d, u, lds);
+    if (!__builtin_amdgcn_readfirstlane(s_skip)) run(d, u, lds);
     if (A.trace && tid == 0) {
       atomicMax((unsigned long long *)&A.trace[3 * t + 1], (unsigned long long)wall_clock64());
       A.trace[3 * t + 2] = blockIdx.x;
@@ -405,19 +487,42 @@ __global__ void __launch_bounds__(GT, 1) dc_gemm_kernel(LevelArgs A) {
   }
 }
 
+// FP64 GEMM/SYRK units (two workgroups per CU).
+__global__ void __launch_bounds__(GT64, 2) dc_gemm_kernel(LevelArgs A) {
+  extern __shared__ double lds[];
+  unit_loop(A, lds, [](const TaskDesc &d, int u, double *l) { run_unit_f64(d, u, l); });
+}
+
+// GEMM/SYRK units with FP32 or BF16 inputs.
+__global__ void __launch_bounds__(GT, 1) dc_gemm_lowp_kernel(LevelArgs A) {
+  extern __shared__ double lds[];
+  unit_loop(A, lds, [](const TaskDesc &d, int u, double *l) { run_unit_lowp(d, u, l); });
+}
+
 constexpr int GEMM_KERNEL_LDS = 2 * STAGE64 * (int)sizeof(double);
-static_assert(2 * STAGE32 * (int)sizeof(float) <= GEMM_KERNEL_LDS, "f32 lds");
-static_assert(2 * STAGE16 * 2 <= GEMM_KERNEL_LDS, "bf16 lds");
+constexpr int GEMM_LOWP_LDS = 2 * STAGE32 * (int)sizeof(float);
+static_assert(2 * STAGE16 * 2 <= GEMM_LOWP_LDS, "bf16 lds");
+static_assert(2 * GEMM_KERNEL_LDS + 64 <= 160 * 1024, "two FP64 workgroups per CU");
 
 }  // namespace
 
 int dcx_launch_gemm(const LevelArgs &args, int workers, void *stream) {
-  hipLaunchKernelGGL(dc_gemm_kernel, dim3(workers), dim3(GT), GEMM_KERNEL_LDS, (hipStream_t)stream,
-                     args);
+  hipLaunchKernelGGL(dc_gemm_kernel, dim3(workers), dim3(GT64), GEMM_KERNEL_LDS,
+                     (hipStream_t)stream, args);
+  return (int)hipGetLastError();
+}
+
+int dcx_launch_gemm_lowp(const LevelArgs &args, int workers, void *stream) {
+  hipLaunchKernelGGL(dc_gemm_lowp_kernel, dim3(workers), dim3(GT), GEMM_LOWP_LDS,
+                     (hipStream_t)stream, args);
   return (int)hipGetLastError();
 }
 
 int dcx_gemm_setup(void) {
-  return (int)hipFuncSetAttribute((const void *)dc_gemm_kernel,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, GEMM_KERNEL_LDS);
+  hipError_t e = hipFuncSetAttribute((const void *)dc_gemm_kernel,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, GEMM_KERNEL_LDS);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void *)dc_gemm_lowp_kernel,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, GEMM_LOWP_LDS);
+  return (int)e;
 }

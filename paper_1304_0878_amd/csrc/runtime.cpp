@@ -172,7 +172,8 @@ extern "C" int dc_shutdown(dc_runtime *rt) {
 
 static int register_common(dc_runtime *rt, dc_handle *out, void *ptr, int64_t rows,
                            int64_t cols, int64_t ld, dc_dtype dtype, int kind) {
-  if (!rt || !out || !ptr || rows < 0 || cols < 0 || ld < cols || ld < 1) return -EINVAL;
+  if (!rt || !out || !ptr || rows < 0 || cols < 0 || ld < cols || ld < 1 || ld > DC_MAX_LD)
+    return -EINVAL;
   if (dtype != DC_F64 && dtype != DC_F32 && dtype != DC_BF16) return -EINVAL;
   if (rt->by_ptr.count(ptr)) return -EBUSY;
   Handle h;
@@ -798,7 +799,10 @@ extern "C" int dc_flush(dc_runtime *rt) {
   // per level: panel-kernel units first, then GEMM/SYRK units
   auto is_gemm = [](const TaskDesc &d) { return d.kind == K_GEMM || d.kind == K_SYRK; };
   int64_t total_units = 0;
-  std::vector<int64_t> pcount(nl, 0), gcount(nl, 0), lcount(nl, 0);
+  // GEMM/SYRK units of a level: FP64 ones first (their own kernel), then
+  // those with FP32/BF16 inputs
+  auto is_g64 = [](const TaskDesc &d) { return d.ta == T_F64; };
+  std::vector<int64_t> pcount(nl, 0), gcount(nl, 0), lcount(nl, 0), g64count(nl, 0);
   std::vector<double> pcost(nl, 0.0), gcost(nl, 0.0);
   const bool timing = rt->ktiming;
   std::vector<double> wflops(timing ? 2 * nl : 0, 0.0), wbytes(timing ? 2 * nl : 0, 0.0);
@@ -806,6 +810,7 @@ extern "C" int dc_flush(dc_runtime *rt) {
     const TaskDesc &d = rt->tasks[t].desc;
     total_units += d.nunits;
     (is_gemm(d) ? gcount : pcount)[level[t]] += d.nunits;
+    if (is_gemm(d) && is_g64(d)) g64count[level[t]] += d.nunits;
     (is_gemm(d) ? gcost : pcost)[level[t]] += cost_ns(d);
     lcount[level[t]] += d.nunits;
     if (timing) {
@@ -823,7 +828,7 @@ extern "C" int dc_flush(dc_runtime *rt) {
   auto take = [&](int64_t bytes) { int64_t o = off; off = align_up(off + bytes, 256); return o; };
   const int64_t o_desc = take(nt * (int64_t)sizeof(TaskDesc));
   const int64_t o_items = take(total_units * 8);
-  const int64_t o_cnt = take(2 * nl * 8);
+  const int64_t o_cnt = take(3 * nl * 8);
   const int64_t o_tail = off;
   const int64_t o_info = take(std::max(nslots_roots, 1) * 8);
   const int64_t o_failed = take(std::max(nslots_roots, 1) * 4);
@@ -861,7 +866,8 @@ extern "C" int dc_flush(dc_runtime *rt) {
     const double cy = cost_ns(rt->tasks[y].desc) / rt->tasks[y].desc.nunits;
     return cx > cy;
   });
-  std::vector<int64_t> fillp(lbegin), fillg(gbegin);
+  std::vector<int64_t> fillp(lbegin), fillg(gbegin), filll(nl);
+  for (int64_t L = 0; L < nl; ++L) filll[L] = gbegin[L] + g64count[L];
   std::vector<size_t> llds(nl, 16);
   for (int64_t i = 0; i < nt; ++i) {
     const int64_t t = order[i];
@@ -870,11 +876,11 @@ extern "C" int dc_flush(dc_runtime *rt) {
     const int L = level[t];
     const bool g = is_gemm(k.desc);
     if (!g) llds[L] = std::max(llds[L], lds_for(k.desc));
-    int64_t &fp = g ? fillg[L] : fillp[L];
+    int64_t &fp = !g ? fillp[L] : is_g64(k.desc) ? fillg[L] : filll[L];
     for (int u = 0; u < k.desc.nunits; ++u)
       items[fp++] = ((uint64_t)(uint32_t)t << 32) | (uint32_t)u;
   }
-  memset(hb + o_cnt, 0, 2 * nl * 8);
+  memset(hb + o_cnt, 0, 3 * nl * 8);
   memset(hb + o_info, 0, std::max(nslots_roots, 1) * 8);
   memset(hb + o_failed, 0, std::max(nslots_roots, 1) * 4);
   if (trace) {
@@ -910,19 +916,26 @@ extern "C" int dc_flush(dc_runtime *rt) {
     a.trace = trace ? (int64_t *)(db + o_trace) : nullptr;
     const bool hasp = pcount[L] > 0, hasg = gcount[L] > 0;
     const int cus = rt->cfg.workers > 0 ? rt->cfg.workers : rt->num_cus;
-    int pworkers = 0;
+    int pworkers = 0, pcus = 0;
     if (hasp) {
       int per_cu = 1;
       dcx_level_occupancy(llds[L], &per_cu);
-      pworkers = (int)std::min<int64_t>(pcount[L], (int64_t)cus * std::max(1, per_cu));
+      pcus = cus;
       if (hasg) {
         // CUs shared in proportion to the estimated work of the two kernels
         const double share = pcost[L] / std::max(1.0, pcost[L] + gcost[L]);
-        const int want = std::max(1, (int)std::ceil(share * cus));
-        pworkers = std::min(pworkers, std::min(want, cus - 1));
+        pcus = std::min(std::max(1, (int)std::ceil(share * cus)), cus - 1);
       }
+      pworkers = (int)std::min<int64_t>(pcount[L], (int64_t)pcus * std::max(1, per_cu));
     }
-    int gworkers = hasg ? (int)std::min<int64_t>(gcount[L], std::max(1, cus - pworkers)) : 0;
+    // CUs left to the GEMM kernels.  Next to the panel kernel, the FP64 GEMM
+    // kernel keeps to one workgroup per CU it is given, so that pcus CUs stay
+    // free for the panel kernel whichever kernel the hardware dispatches
+    // first (a panel workgroup needs a whole CU's registers); alone it runs
+    // two workgroups per CU.
+    const int gcus = hasp ? std::max(1, cus - pcus) : cus;
+    const int g64_per_cu = hasp ? 1 : 2;
+    int gworkers = 0;
     hipStream_t pstream = rt->stream;
     if (hasp && hasg) {
       // fork: the panel units run on the side stream next to the GEMM units
@@ -938,7 +951,7 @@ extern "C" int dc_flush(dc_runtime *rt) {
     if (hasp) {
       a.begin = lbegin[L];
       a.count = pcount[L];
-      a.counter = (unsigned long long *)(db + o_cnt) + 2 * L;
+      a.counter = (unsigned long long *)(db + o_cnt) + 3 * L;
       const size_t tb = timing ? tev(pstream) : 0;
       int le = dcx_launch_level(a, pworkers, llds[L], pstream);
       if (le != 0) { fail_hip((hipError_t)le, "level launch"); drop(); return -EIO; }
@@ -949,12 +962,26 @@ extern "C" int dc_flush(dc_runtime *rt) {
       }
     }
     if (hasg) {
-      a.begin = gbegin[L];
-      a.count = gcount[L];
-      a.counter = (unsigned long long *)(db + o_cnt) + 2 * L + 1;
       const size_t tb = timing ? tev(rt->stream) : 0;
-      int le = dcx_launch_gemm(a, gworkers, rt->stream);
-      if (le != 0) { fail_hip((hipError_t)le, "gemm launch"); drop(); return -EIO; }
+      const int64_t n64 = g64count[L], nlp = gcount[L] - g64count[L];
+      if (n64 > 0) {
+        a.begin = gbegin[L];
+        a.count = n64;
+        a.counter = (unsigned long long *)(db + o_cnt) + 3 * L + 1;
+        const int wg = (int)std::min<int64_t>(n64, (int64_t)g64_per_cu * gcus);
+        gworkers = std::max(gworkers, wg);
+        int le = dcx_launch_gemm(a, wg, rt->stream);
+        if (le != 0) { fail_hip((hipError_t)le, "gemm launch"); drop(); return -EIO; }
+      }
+      if (nlp > 0) {
+        a.begin = gbegin[L] + n64;
+        a.count = nlp;
+        a.counter = (unsigned long long *)(db + o_cnt) + 3 * L + 2;
+        const int wg = (int)std::min<int64_t>(nlp, gcus);
+        gworkers = std::max(gworkers, wg);
+        int le = dcx_launch_gemm_lowp(a, wg, rt->stream);
+        if (le != 0) { fail_hip((hipError_t)le, "gemm launch"); drop(); return -EIO; }
+      }
       if (timing) {
         const size_t te = tev(rt->stream);
         if (tb == SIZE_MAX || te == SIZE_MAX) { drop(); return -EIO; }
