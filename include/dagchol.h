@@ -93,6 +93,18 @@ typedef enum { DC_F64 = 0, DC_F32 = 1, DC_BF16 = 2 } dc_dtype;
  *   DC_AXPY       (D:R, X:RW)       X <- X + D, FP64 matrices of one shape.
  *   DC_TRSM_CAST  (L:R, X:RW, S:W)  TRSM on an FP32 tile X that also writes
  *                                   S = BF16(X) (round to nearest even).
+ *   DC_TRTRI      (L:R, W:W)        lower(W) <- L^{-1}, L lower non-unit,
+ *                                   FP64, order 16..512.  The strictly upper
+ *                                   part of W is scratch: it receives
+ *                                   max |L| and per-column-block max |W|.
+ *   DC_TRSM_INV   (L:R, W:R, X:RW)  X <- X L^{-T} computed as X W^T with W
+ *                                   from DC_TRTRI of the same L (a dense
+ *                                   MFMA product instead of a substitution).
+ *                                   When max |L| * max |W| > 1024 (an
+ *                                   ill-conditioned L, where the explicit
+ *                                   inverse would lose accuracy) it solves
+ *                                   with L by substitution like DC_TRSM.
+ *                                   X FP64 or FP32.
  * Precisions (the dtypes of the handles select the kernel):
  *   POTRF: FP64.  TRSM: L FP64, X FP64 or FP32 (FP64 arithmetic, FP32 tiles
  *   rounded on store).  SYRK/GEMM: FP64 inputs update FP64 tiles with FP64
@@ -104,7 +116,8 @@ typedef enum {
   DC_POTRF = 0, DC_TRSM = 1, DC_SYRK = 2, DC_GEMM = 3,
   DC_TRSM_L = 4, DC_GEMM_RHS_N = 5, DC_TRSM_LT = 6, DC_GEMM_RHS_T = 7,
   DC_SCAL = 8, DC_CAST = 9, DC_RESID = 10, DC_AXPY = 11, DC_TRSM_CAST = 12,
-  DC_NUM_KINDS = 13
+  DC_TRTRI = 13, DC_TRSM_INV = 14,
+  DC_NUM_KINDS = 15
 } dc_kind;
 
 typedef struct {
@@ -274,7 +287,12 @@ int dc_kernel_stats_get(dc_runtime *rt, dc_kernel_stats *out);
  *
  * dc_potrf: tiled right-looking Cholesky of the lower triangle of A in
  * place, in FP64: for k, POTRF(k); TRSM(i,k) for i>k; SYRK(i,k) and
- * GEMM(i,j,k) for k<j<i.  Result: dc_get_info(A). */
+ * GEMM(i,j,k) for k<j<i.  Result: dc_get_info(A).  With tile >= 16 the
+ * panel solves of column k are TRTRI(k) into a workspace W_k followed by
+ * TRSM_INV(i,k) for i>k (same result up to rounding; ill-conditioned
+ * diagonal tiles fall back to substitution, see DC_TRSM_INV).  The runtime
+ * keeps the workspace, (tiles - 1) * tile^2 doubles, until dc_shutdown;
+ * -ENOMEM if it cannot be allocated. */
 int dc_potrf(dc_runtime *rt, dc_handle A, int64_t tile);
 
 /* dc_potrs: solves L L^T X = B in place in B (n x r, FP64) with the factor

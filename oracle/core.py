@@ -30,6 +30,8 @@ def lib():
             "or_potrf_tile": (_I64, [_I64, _D, _I64]),
             "or_trsm_tile": (None, [_I64, _I64, _D, _I64, _D, _I64]),
             "or_gemm_tile": (None, [_I64, _I64, _I64, _D, _I64, _D, _I64, _D, _I64]),
+            "or_trtri_tile": (None, [_I64, _D, _I64, _D, _I64]),
+            "or_trsm_inv_tile": (None, [_I64, _I64, _D, _I64, _D, _I64]),
             "or_syrk_tile": (None, [_I64, _I64, _D, _I64, _D, _I64]),
             "or_trsm_left_tile": (None, [_I64, _I64, _D, _I64, _D, _I64]),
             "or_trsm_left_t_tile": (None, [_I64, _I64, _D, _I64, _D, _I64]),
@@ -87,6 +89,21 @@ def trsm_tile(l, x):
     """X <- X L^{-T} (right, lower, transposed, non-unit)."""
     l, x = _f64(l), _f64(x).copy()
     lib().or_trsm_tile(x.shape[0], x.shape[1], _p(l), l.shape[1], _p(x), x.shape[1])
+    return x
+
+
+def trtri_tile(l):
+    """W = L^{-1} for lower-triangular L (non-unit); W's upper part is zero."""
+    l = _f64(l)
+    w = np.zeros_like(l)
+    lib().or_trtri_tile(l.shape[0], _p(l), l.shape[1], _p(w), w.shape[1])
+    return w
+
+
+def trsm_inv_tile(w, x):
+    """X <- X W^T with W lower triangular (only W's lower part is read)."""
+    w, x = _f64(w), _f64(x).copy()
+    lib().or_trsm_inv_tile(x.shape[0], x.shape[1], _p(w), w.shape[1], _p(x), x.shape[1])
     return x
 
 

@@ -103,6 +103,48 @@ void or_trsm_tile(int64_t m, int64_t nb, const double *l, int64_t ldl,
     }
 }
 
+/* Inverse of a lower-triangular tile: lower(W) <- L^{-1}, column by column.
+ * Column j of W solves L w = e_j by forward substitution; its entries above
+ * row j are zero and are not stored (the strictly upper part of W is left
+ * as it was).  w_i = (delta_ij - sum_{j<=p<i} l_ip w_p) / l_ii, p increasing. */
+void or_trtri_tile(int64_t nb, const double *l, int64_t ldl, double *w, int64_t ldw)
+{
+#pragma omp parallel for schedule(static) if (nb > 64)
+    for (int64_t j = 0; j < nb; ++j) {
+        for (int64_t i = j; i < nb; ++i) {
+            double t = (i == j) ? 1.0 : 0.0;
+            for (int64_t p = j; p < i; ++p) {
+                double prod = AT(l, ldl, i, p) * AT(w, ldw, p, j);
+                t = t - prod;
+            }
+            AT(w, ldw, i, j) = t / AT(l, ldl, i, i);
+        }
+    }
+}
+
+/* The panel solve through an explicit inverse: X <- X W^T with W lower
+ * triangular (W = L^{-1} gives X L^{-T}).  x_ic = sum_{p<=c} x_ip w_cp, p
+ * increasing, on a copy of the row. */
+void or_trsm_inv_tile(int64_t m, int64_t nb, const double *w, int64_t ldw,
+                      double *x, int64_t ldx)
+{
+#pragma omp parallel for schedule(static) if (m > 64)
+    for (int64_t i = 0; i < m; ++i) {
+        double *row = x + i * ldx;
+        double *in = (double *)malloc((size_t)nb * sizeof(double));
+        memcpy(in, row, (size_t)nb * sizeof(double));
+        for (int64_t c = 0; c < nb; ++c) {
+            double t = 0.0;
+            for (int64_t p = 0; p <= c; ++p) {
+                double prod = in[p] * AT(w, ldw, c, p);
+                t = t + prod;
+            }
+            row[c] = t;
+        }
+        free(in);
+    }
+}
+
 /* GEMM update of an off-diagonal tile: C <- C - X Y^T, with X (m x kb) and
  * Y (nn x kb).  Every c_ij receives its kb subtractions in increasing p.
  * Y is first copied into a transposed scratch (a copy, no arithmetic) so the

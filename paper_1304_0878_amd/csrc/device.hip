@@ -93,13 +93,37 @@ __device__ __forceinline__ void wave_sync() {
 // staged in LDS; (1) X_J -= X_{<J} L_{J,<J}^T with MFMA, wave w producing
 // columns 4w..4w+3 for all 16 rows; (2) one thread per row solves the 16x16
 // lower-triangular system with L_JJ (divisions by the diagonal).
-__device__ __forceinline__ void run_trsm(const TaskDesc &d, int unit, double *lds) {
+//
+// With TRTRI the same substitution inverts L: the 16 rows are rows
+// 16u..16u+15 of the identity, so X becomes rows of L^{-T}, i.e. columns of
+// W = L^{-1}, stored transposed into W's lower triangle.  Those rows are zero
+// left of column 16u, so the blocks and the update terms left of it are
+// skipped.  Each unit also records max |W| over its columns in W[0][1 + u],
+// and unit 0, which reads all of L's lower triangle, max |L| in W[1][2]: the
+// strictly upper part of W is otherwise unused and is never written by the
+// transposed store.
+constexpr int INV_SLOT_ROW_W = 0;   // W[0][1 + u]: max |W| of unit u's columns
+constexpr int INV_SLOT_L = 1;       // W[1][2]: max |L| over the lower triangle
+
+// Largest value over the workgroup (all threads return it).
+__device__ __forceinline__ double block_max(double v, double *red) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  v = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+  __syncthreads();
+  return v;
+}
+
+template <bool TRTRI>
+__device__ __forceinline__ void trsm_core(const TaskDesc &d, int unit, double *lds,
+                                          const gdouble *L, int64_t ldl) {
   const int nb = d.n;
   const int r0 = unit * TRSM_ROWS;
   const int rows = min(TRSM_ROWS, d.m - r0);
   const int XS = panel_stride(nb);
-  const gdouble *L = (const gdouble *)d.a;
-  const int64_t ldl = d.lda;
   gdouble *X = (gdouble *)d.c + (int64_t)r0 * d.ldc;
   const int64_t ldc = d.ldc;
   double *Xs = lds;                          // 16 x XS
@@ -113,30 +137,47 @@ __device__ __forceinline__ void run_trsm(const TaskDesc &d, int unit, double *ld
   const int kq = lane >> 4;
   const int n4 = lane & 3;
 
-  const bool x32 = d.tc == T_F32;
+  const bool x32 = !TRTRI && d.tc == T_F32;
   gfloat *X32 = (gfloat *)d.c + (int64_t)r0 * d.ldc;
-  if (x32)
+  if (TRTRI) {
+    for (int idx = tid; idx < TRSM_ROWS * nb; idx += NT) {
+      const int r = idx / nb, c = idx - r * nb;
+      Xs[r * XS + c] = (r < rows && c == r0 + r) ? 1.0 : 0.0;
+    }
+  } else if (x32) {
     stage16<float>(Xs, XS, X32, ldc, rows, nb);
-  else
+  } else {
     stage16<double>(Xs, XS, X, ldc, rows, nb);
+  }
+  // identity rows are zero left of r0: neither blocks nor update terms
+  // there contribute
+  const int kstart = TRTRI ? r0 : 0;
+  double lmax = 0.0;
   const int nj = (nb + PANEL - 1) / PANEL;
-  for (int J = 0; J < nj; ++J) {
+  for (int J = TRTRI ? unit : 0; J < nj; ++J) {
     const int c0 = PANEL * J;
     const int wj = min(PANEL, nb - c0);
-    // rows c0..c0+15 of L, columns 0..c0+15 (the block left of the diagonal
-    // and the diagonal block itself)
-    stage16<double>(Lp, XS, L + (int64_t)c0 * ldl, ldl, wj, c0 + wj);
+    // rows c0..c0+15 of L, columns kstart..c0+15 (the block left of the
+    // diagonal and the diagonal block itself)
+    stage16<double>(Lp + kstart, XS, L + (int64_t)c0 * ldl + kstart, ldl, wj, c0 + wj - kstart);
     __syncthreads();
     {
       const int i = tid >> 4, j = tid & 15;
       Ljj[i * (PANEL + 1) + j] = (i < wj && j <= i) ? Lp[i * XS + c0 + j] : 0.0;
     }
+    if (TRTRI && unit == 0) {
+      // lower-triangle entries of the staged rows
+      for (int idx = tid; idx < PANEL * (c0 + PANEL); idx += NT) {
+        const int i = idx / (c0 + PANEL), c = idx - i * (c0 + PANEL);
+        if (i < wj && c <= c0 + i) lmax = fmax(lmax, fabs(Lp[i * XS + c]));
+      }
+    }
     __syncthreads();
-    if (c0 > 0) {
+    if (c0 > kstart) {
       double acc = 0.0;
       const double *xa = Xs + l16 * XS + kq;
       const double *lb = Lp + (4 * w + n4) * XS + kq;
-      for (int k0 = 0; k0 < c0; k0 += 16) {
+      for (int k0 = kstart; k0 < c0; k0 += 16) {
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc = mfma44(xa[k0 + 4 * j], lb[k0 + 4 * j], acc);
       }
@@ -165,6 +206,26 @@ __device__ __forceinline__ void run_trsm(const TaskDesc &d, int unit, double *ld
     }
     __syncthreads();
   }
+  if (TRTRI) {
+    // W[c][r0 + r] = X[r][c] on and below the diagonal; 16 consecutive
+    // threads write 16 consecutive entries of one row of W
+    double wmax = 0.0;
+    for (int idx = tid; idx < TRSM_ROWS * nb; idx += NT) {
+      const int r = idx & 15, c = idx >> 4;
+      if (r < rows && c >= r0 + r) {
+        const double v = Xs[r * XS + c];
+        wmax = fmax(wmax, fabs(v));
+        ((gdouble *)d.c)[(int64_t)c * ldc + r0 + r] = v;
+      }
+    }
+    wmax = block_max(wmax, Ljj);
+    lmax = block_max(lmax, Ljj);
+    if (tid == 0) {
+      ((gdouble *)d.c)[(int64_t)INV_SLOT_ROW_W * ldc + 1 + unit] = wmax;
+      if (unit == 0) ((gdouble *)d.c)[(int64_t)INV_SLOT_L * ldc + 2] = lmax;
+    }
+    return;
+  }
   typedef __attribute__((address_space(1))) __bf16 gbf16;
   gbf16 *S16 = d.d ? (gbf16 *)d.d + (int64_t)r0 * d.ldd : nullptr;
   for (int idx = tid; idx < rows * nb; idx += NT) {
@@ -176,6 +237,141 @@ __device__ __forceinline__ void run_trsm(const TaskDesc &d, int unit, double *ld
     } else {
       X[(int64_t)r * ldc + c] = Xs[r * XS + c];
     }
+  }
+}
+
+__device__ __forceinline__ void run_trsm(const TaskDesc &d, int unit, double *lds) {
+  trsm_core<false>(d, unit, lds, (const gdouble *)d.a, d.lda);
+}
+
+// ------------------------------------------------------------- TRSM_INV
+//
+// X (m x nb) <- X W^T with W = L^{-1} from a TRTRI task: a dense product, so
+// the substitution's column-by-column dependence disappears.  Unit = 16 rows
+// of X staged in LDS; wave w produces the 16x16 output blocks b = w + 4i
+// (interleaved so the triangular work is balanced over the waves) with
+// 16x16x4 FP64 MFMA.  Block b only needs K chunks kc <= b (W is lower
+// triangular); W's rows are streamed from global memory straight into the
+// B operand, the next chunk's loads in flight while the current one is
+// multiplied.  Inside a chunk, lane group kq takes the four consecutive k
+// 4kq..4kq+3 (one 32-byte load per row) for the four MFMA steps, and the A
+// operand follows the same order.
+//
+// The explicit inverse multiplies rounding errors by about max|L| max|W|;
+// when the slots TRTRI recorded put that product above INV_LIMIT (or it is
+// not finite) the unit solves with L by substitution instead, as a TRSM
+// unit would, so ill-conditioned diagonal tiles keep the substitution's
+// accuracy.
+constexpr double INV_LIMIT = 1024.0;
+
+template <bool FULL>
+__device__ __forceinline__ void trsm_inv_product(const TaskDesc &d, int unit, double *lds) {
+  const int nb = d.n;
+  const int nb16 = (nb + 15) / 16;
+  const int r0 = unit * TRSM_ROWS;
+  const int rows = min(TRSM_ROWS, d.m - r0);
+  const int XS = panel_stride(nb);
+  const gdouble *W = (const gdouble *)d.a;
+  const int64_t ldw = d.lda;
+  const int64_t ldc = d.ldc;
+  const bool x32 = d.tc == T_F32;
+  double *Xs = lds;
+  if (x32)
+    stage16<float>(Xs, XS, (gfloat *)d.c + (int64_t)r0 * ldc, ldc, rows, nb);
+  else
+    stage16<double>(Xs, XS, (gdouble *)d.c + (int64_t)r0 * ldc, ldc, rows, nb);
+  __syncthreads();
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int l16 = lane & 15, kq = lane >> 4;
+  typedef double dvec4 __attribute__((ext_vector_type(4)));
+  dvec4 acc[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) acc[i] = dvec4{0.0, 0.0, 0.0, 0.0};
+  // B operand of block b, chunk kc: W[16b + l16][16kc + 4kq + s], s < 4
+  auto wload = [&](int kc, double (&v)[8][4]) {
+    const int k = 16 * kc + 4 * kq;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int b = w + 4 * i;
+      if (b >= kc && b < nb16) {
+        const int row = 16 * b + l16;
+        if (FULL) {
+          const gdvec2 *p = (const gdvec2 *)(W + (int64_t)row * ldw + k);
+          const dvec2 x0 = p[0], x1 = p[1];
+          v[i][0] = x0[0]; v[i][1] = x0[1]; v[i][2] = x1[0]; v[i][3] = x1[1];
+        } else {
+#pragma unroll
+          for (int s = 0; s < 4; ++s)
+            v[i][s] = (row < nb && k + s < nb) ? W[(int64_t)row * ldw + k + s] : 0.0;
+        }
+        if (b == kc) {   // diagonal chunk: only k <= row is part of W
+#pragma unroll
+          for (int s = 0; s < 4; ++s)
+            if (4 * kq + s > l16) v[i][s] = 0.0;
+        }
+      }
+    }
+  };
+  auto chunk = [&](int kc, const double (&v)[8][4]) {
+    double a[4];
+    const int k = 16 * kc + 4 * kq;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) a[s] = (FULL || k + s < nb) ? Xs[l16 * XS + k + s] : 0.0;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int b = w + 4 * i;
+      if (b >= kc && b < nb16) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+          acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], v[i][s], acc[i], 0, 0, 0);
+      }
+    }
+  };
+  // two register sets alternate: the loads of one chunk are in flight while
+  // the other is multiplied
+  double wa[8][4], wb[8][4];
+  wload(0, wa);
+  for (int kc = 0; kc < nb16; kc += 2) {
+    if (kc + 1 < nb16) wload(kc + 1, wb);
+    chunk(kc, wa);
+    if (kc + 2 < nb16) wload(kc + 2, wa);
+    if (kc + 1 < nb16) chunk(kc + 1, wb);
+  }
+  // result element e of lane l: row l/16 + 4e, column l%16 of block b
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const int b = w + 4 * i;
+    const int col = 16 * b + l16;
+    if (b < nb16 && col < nb) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int row = kq + 4 * e;
+        if (row < rows) {
+          if (x32)
+            ((gfloat *)d.c)[(int64_t)(r0 + row) * ldc + col] = (float)acc[i][e];
+          else
+            ((gdouble *)d.c)[(int64_t)(r0 + row) * ldc + col] = acc[i][e];
+        }
+      }
+    }
+  }
+}
+
+__device__ __forceinline__ void run_trsm_inv(const TaskDesc &d, int unit, double *lds) {
+  const int nb = d.n;
+  const int nb16 = (nb + 15) / 16;
+  const gdouble *W = (const gdouble *)d.a;
+  double wmax = 0.0;
+  for (int u = 0; u < nb16; ++u) wmax = fmax(wmax, W[(int64_t)INV_SLOT_ROW_W * d.lda + 1 + u]);
+  const double lmax = W[(int64_t)INV_SLOT_L * d.lda + 2];
+  const double amp = wmax * lmax;
+  const int use_inverse = __builtin_amdgcn_readfirstlane(amp <= INV_LIMIT ? 1 : 0);
+  if (!use_inverse) {
+    trsm_core<false>(d, unit, lds, (const gdouble *)d.b, d.ldb);
+  } else if (nb % 16 == 0 && d.lda % 2 == 0 && ((uintptr_t)d.a & 15) == 0) {
+    trsm_inv_product<true>(d, unit, lds);
+  } else {
+    trsm_inv_product<false>(d, unit, lds);
   }
 }
 
@@ -902,6 +1098,8 @@ __global__ void __launch_bounds__(NT, 1) dc_level_kernel(LevelArgs A) {
     if (!skip) {
       switch (kind) {
         case K_TRSM: case K_TRSM_CAST: run_trsm(d, u, lds); break;
+        case K_TRTRI: trsm_core<true>(d, u, lds, (const gdouble *)d.a, d.lda); break;
+        case K_TRSM_INV: run_trsm_inv(d, u, lds); break;
         case K_POTRF: {
           const int bad = run_potrf(d, lds);
           if (bad && tid == 0 && d.matrix >= 0) {

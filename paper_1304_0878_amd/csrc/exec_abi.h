@@ -11,7 +11,8 @@ enum Kind : int32_t {
   K_POTRF = 0, K_TRSM = 1, K_SYRK = 2, K_GEMM = 3,
   K_TRSM_L = 4, K_GEMM_RHS_N = 5, K_TRSM_LT = 6, K_GEMM_RHS_T = 7,
   K_SCAL = 8, K_CAST = 9, K_RESID = 10, K_AXPY = 11, K_TRSM_CAST = 12,
-  K_NUM = 13
+  K_TRTRI = 13, K_TRSM_INV = 14,
+  K_NUM = 15
 };
 
 enum DType : int32_t { T_F64 = 0, T_F32 = 1, T_BF16 = 2 };

@@ -38,8 +38,11 @@ template <typename T> using gp = __attribute__((address_space(1))) T *;
 
 // ------------------------------------------------------------------ FP64
 //
-// FP64 units run in their own kernel: 256 threads (four waves in a 2 x 2
-// grid of 64 x 64 tiles), two workgroups per CU, 16x16x4 FP64 MFMA (lane l
+// FP64 units run in their own kernel, one 512-thread workgroup per CU made
+// of two halves that each compute one unit of the same task (four waves in
+// a 2 x 2 grid of 64 x 64 tiles): two waves per SIMD, yet a single
+// workgroup per CU, so the kernel never takes the CUs the panel kernel was
+// left.  16x16x4 FP64 MFMA (lane l
 // supplies A[l%16][l/16] and B^T[l/16][l%16]; result element e of lane l is
 // D[l/16 + 4e][l%16]).  K chunks of 16 are staged in LDS, double buffered,
 // with an odd row stride (17 doubles): the 16 lanes that read one fragment
@@ -47,7 +50,7 @@ template <typename T> using gp = __attribute__((address_space(1))) T *;
 // C is pre-loaded negated into the accumulators, so the epilogue is a plain
 // store of the negation.
 
-constexpr int GT64 = 256;
+constexpr int GT64 = 512;                     // two halves of 256 threads
 constexpr int KC64 = 16;
 constexpr int S64 = KC64 + 1;                 // doubles per LDS row
 constexpr int STAGE64 = 2 * GEMM_UNIT * S64;  // A and B of one stage
@@ -94,8 +97,8 @@ __device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, uint32_t voff, 
 template <bool FULL>
 __device__ __forceinline__ void block_f64(void *C, int64_t ldc, const void *A, int64_t lda,
                                           const void *B, int64_t ldb, int M, int N, int K,
-                                          int dlim, double *lds) {
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+                                          int dlim, double *lds, int tid) {
+  const int lane = tid & 63, w = tid >> 6;
   const int wr = w >> 1, wc = w & 1;
   const int l16 = lane & 15, kq = lane >> 4;
   const int r0 = 64 * wr + kq, c0 = 64 * wc + l16;  // element (i, j, e) at r0 + 16i + 4e, c0 + 16j
@@ -413,7 +416,7 @@ __device__ __forceinline__ UnitBlock unit_block(const TaskDesc &d, int unit, int
   return u;
 }
 
-__device__ __forceinline__ void run_unit_f64(const TaskDesc &d, int unit, double *lds) {
+__device__ __forceinline__ void run_unit_f64(const TaskDesc &d, int unit, double *lds, int tid) {
   const UnitBlock u = unit_block(d, unit, 8);
   // buffer resources must sit in scalar registers: make the wave-uniform
   // unit fields provably uniform so no per-lane resource loop is generated
@@ -426,9 +429,23 @@ __device__ __forceinline__ void run_unit_f64(const TaskDesc &d, int unit, double
   const int K = __builtin_amdgcn_readfirstlane(d.k);
   const int dlim = __builtin_amdgcn_readfirstlane(u.lower_only ? 0 : GEMM_UNIT);
   if (M == GEMM_UNIT && N == GEMM_UNIT && K % KC64 == 0)
-    block_f64<true>(C, ldc, a, lda, b, ldb, M, N, K, dlim, lds);
+    block_f64<true>(C, ldc, a, lda, b, ldb, M, N, K, dlim, lds, tid);
   else
-    block_f64<false>(C, ldc, a, lda, b, ldb, M, N, K, dlim, lds);
+    block_f64<false>(C, ldc, a, lda, b, ldb, M, N, K, dlim, lds, tid);
+}
+
+// One work item of the FP64 kernel: units u0 and u0 + 1 of one task, one per
+// half.  Both have the task's K and so pass the same number of workgroup
+// barriers; a half without a unit (odd unit count) only passes them.
+__device__ __forceinline__ void run_pair_f64(const TaskDesc &d, int u0, double *lds) {
+  const int half = threadIdx.x >> 8, tid = threadIdx.x & 255;
+  const int unit = u0 + half;
+  if (unit < __builtin_amdgcn_readfirstlane(d.nunits)) {
+    run_unit_f64(d, unit, lds + half * 2 * STAGE64, tid);
+  } else {
+    const int nst = (__builtin_amdgcn_readfirstlane(d.k) + KC64 - 1) / KC64;
+    for (int i = 0; i <= nst; ++i) __syncthreads();
+  }
 }
 
 __device__ __forceinline__ void run_unit_lowp(const TaskDesc &d, int unit, double *lds) {
@@ -488,9 +505,9 @@ __device__ __forceinline__ void unit_loop(const LevelArgs &A, double *lds, RUN r
 }
 
 // FP64 GEMM/SYRK units (two workgroups per CU).
-__global__ void __launch_bounds__(GT64, 2) dc_gemm_kernel(LevelArgs A) {
+__global__ void __launch_bounds__(GT64, 1) dc_gemm_kernel(LevelArgs A) {
   extern __shared__ double lds[];
-  unit_loop(A, lds, [](const TaskDesc &d, int u, double *l) { run_unit_f64(d, u, l); });
+  unit_loop(A, lds, [](const TaskDesc &d, int u, double *l) { run_pair_f64(d, u, l); });
 }
 
 // GEMM/SYRK units with FP32 or BF16 inputs.
@@ -499,10 +516,10 @@ __global__ void __launch_bounds__(GT, 1) dc_gemm_lowp_kernel(LevelArgs A) {
   unit_loop(A, lds, [](const TaskDesc &d, int u, double *l) { run_unit_lowp(d, u, l); });
 }
 
-constexpr int GEMM_KERNEL_LDS = 2 * STAGE64 * (int)sizeof(double);
+constexpr int GEMM_KERNEL_LDS = 2 * 2 * STAGE64 * (int)sizeof(double);   // two halves
 constexpr int GEMM_LOWP_LDS = 2 * STAGE32 * (int)sizeof(float);
 static_assert(2 * STAGE16 * 2 <= GEMM_LOWP_LDS, "bf16 lds");
-static_assert(2 * GEMM_KERNEL_LDS + 64 <= 160 * 1024, "two FP64 workgroups per CU");
+static_assert(GEMM_KERNEL_LDS + 64 <= 160 * 1024, "FP64 workgroup LDS");
 
 }  // namespace
 

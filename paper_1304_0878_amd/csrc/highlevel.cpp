@@ -33,9 +33,11 @@ struct Tiles {
     return e;
   }
   dc_handle at(int64_t i, int64_t j) const { return ids[i * tc + j]; }
-  ~Tiles() {
+  void close() {
     if (active) dc_matrix_unpartition(rt, m);
+    active = false;
   }
+  ~Tiles() { close(); }
 };
 
 int submit1(dc_runtime *rt, dc_kind k, dc_handle a, dc_mode ma, int prio,
@@ -71,13 +73,23 @@ void dcx_discard_pending(dc_runtime *rt) {
 
 // Right-looking tiled factorisation on partitioned tiles (submission only).
 // Priorities (Section 5.3's hints): the diagonal factor, the panel TRSMs and
-// the updates of the next panel column come first.
-int dcx_submit_potrf_tiles(dc_runtime *rt, const std::vector<dc_handle> &A, int64_t T) {
+// the updates of the next panel column come first.  With inverse workspaces
+// W (one per diagonal tile but the last), the panel solves of column k are
+// TRTRI(k) followed by TRSM_INV(i, k).
+int dcx_submit_potrf_tiles(dc_runtime *rt, const std::vector<dc_handle> &A, int64_t T,
+                           const std::vector<dc_handle> *W) {
   auto at = [&](int64_t i, int64_t j) { return A[i * T + j]; };
   for (int64_t k = 0; k < T; ++k) {
     TRY(submit1(rt, DC_POTRF, at(k, k), DC_RW, 0));
-    for (int64_t i = k + 1; i < T; ++i)
-      TRY(submit2(rt, DC_TRSM, at(k, k), DC_R, at(i, k), DC_RW, i == k + 1 ? 0 : 1));
+    if (W && k + 1 < T) {
+      TRY(submit2(rt, DC_TRTRI, at(k, k), DC_R, (*W)[k], DC_W, 0));
+      for (int64_t i = k + 1; i < T; ++i)
+        TRY(submit3(rt, DC_TRSM_INV, at(k, k), DC_R, (*W)[k], DC_R, at(i, k), DC_RW,
+                    i == k + 1 ? 0 : 1));
+    } else {
+      for (int64_t i = k + 1; i < T; ++i)
+        TRY(submit2(rt, DC_TRSM, at(k, k), DC_R, at(i, k), DC_RW, i == k + 1 ? 0 : 1));
+    }
     for (int64_t i = k + 1; i < T; ++i) {
       TRY(submit2(rt, DC_SYRK, at(i, k), DC_R, at(i, i), DC_RW, i == k + 1 ? 0 : 2));
       for (int64_t j = k + 1; j < i; ++j)
@@ -113,11 +125,47 @@ extern "C" int dc_potrf(dc_runtime *rt, dc_handle A, int64_t tile) {
     return -EINVAL;
   if (p->partitioned) return -EBUSY;
   if (p->rows == 0) { p->info = 0; return 0; }
-  Tiles t;
-  TRY(t.open(rt, A, tile));
-  int e = dcx_submit_potrf_tiles(rt, t.ids, t.tr);
-  if (e) { dcx_discard_pending(rt); return e; }
-  return dc_wait_all(rt);
+  const int64_t n = p->rows;
+  const int64_t T = (n + tile - 1) / tile;
+  // inverse workspaces: tiles - 1 full diagonal tiles, kept by the runtime
+  const bool inv = tile >= 16 && T > 1 && rt->cfg.device >= 0;
+  dc_handle wh = 0;
+  Tiles tw;
+  if (inv) {
+    const int64_t bytes = (T - 1) * tile * tile * 8;
+    if (rt->inv_ws_bytes < bytes) {
+      if (rt->inv_ws) {
+        if (hipStreamSynchronize(rt->stream) != hipSuccess) return -EIO;
+        hipFree(rt->inv_ws);
+        rt->inv_ws = nullptr;
+        rt->inv_ws_bytes = 0;
+      }
+      if (hipMalloc(&rt->inv_ws, bytes) != hipSuccess) {
+        rt->inv_ws = nullptr;
+        return -ENOMEM;
+      }
+      rt->inv_ws_bytes = bytes;
+    }
+    TRY(dc_matrix_register(rt, &wh, rt->inv_ws, (T - 1) * tile, tile, tile, DC_F64));
+    const int e = tw.open(rt, wh, tile);
+    if (e) { dc_unregister(rt, wh); return e; }
+  }
+  int e;
+  {
+    Tiles t;
+    e = t.open(rt, A, tile);
+    if (!e) {
+      e = dcx_submit_potrf_tiles(rt, t.ids, t.tr, inv ? &tw.ids : nullptr);
+      if (e) dcx_discard_pending(rt);
+      else e = dc_wait_all(rt);
+    }
+  }
+  if (inv) {
+    tw.close();
+    const int e2 = dc_unregister(rt, wh);
+    if (!e) e = e2;
+  }
+  return e;
 }
 
 extern "C" int dc_potrs(dc_runtime *rt, dc_handle L, dc_handle B, int64_t tile) {
@@ -172,7 +220,7 @@ extern "C" int dc_potrf_batched(dc_runtime *rt, int64_t count, const dc_handle *
     if (p->rows == 0) continue;
     const int64_t tile = tiles[i] > 0 ? std::min<int64_t>(tiles[i], p->rows) : p->rows;
     err = ta[i].open(rt, A[i], tile);
-    if (!err) err = dcx_submit_potrf_tiles(rt, ta[i].ids, ta[i].tr);
+    if (!err) err = dcx_submit_potrf_tiles(rt, ta[i].ids, ta[i].tr, nullptr);
     if (!err && B && B[i] && rt->get(B[i])->cols > 0) {
       err = tb[i].open(rt, B[i], tile);
       std::vector<dc_handle> rows(ta[i].tr);

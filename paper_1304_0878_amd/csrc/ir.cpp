@@ -18,7 +18,8 @@
 #include "../../include/dagchol.h"
 #include "runtime_internal.h"
 
-int dcx_submit_potrf_tiles(dc_runtime *rt, const std::vector<dc_handle> &A, int64_t T);
+int dcx_submit_potrf_tiles(dc_runtime *rt, const std::vector<dc_handle> &A, int64_t T,
+                           const std::vector<dc_handle> *W);
 int dcx_submit_potrs_tiles(dc_runtime *rt, const std::vector<dc_handle> &L, int64_t T,
                            const std::vector<dc_handle> &B);
 

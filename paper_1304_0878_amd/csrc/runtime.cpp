@@ -159,6 +159,7 @@ extern "C" int dc_shutdown(dc_runtime *rt) {
   if (rt->cfg.device >= 0) {
     err = dc_wait_all(rt);
     free_device(rt);
+    if (rt->inv_ws) hipFree(rt->inv_ws);
     for (hipEvent_t e : rt->events) hipEventDestroy(e);
     for (hipEvent_t e : rt->tevents) hipEventDestroy(e);
     if (rt->side) hipStreamDestroy(rt->side);
@@ -351,6 +352,8 @@ static const KindSig kSig[DC_NUM_KINDS] = {
     {4, {DC_R, DC_R, DC_R, DC_W}},      // RESID
     {2, {DC_R, DC_RW}},                 // AXPY
     {3, {DC_R, DC_RW, DC_W}},           // TRSM_CAST
+    {2, {DC_R, DC_W}},                  // TRTRI
+    {3, {DC_R, DC_R, DC_RW}},           // TRSM_INV
 };
 
 static int units_for(const TaskDesc &d) {
@@ -358,7 +361,8 @@ static int units_for(const TaskDesc &d) {
   switch (d.kind) {
     case K_GEMM: return std::max(1, cdiv(d.m, GEMM_UNIT) * cdiv(d.n, GEMM_UNIT));
     case K_SYRK: { int p = cdiv(d.m, GEMM_UNIT); return std::max(1, p * (p + 1) / 2); }
-    case K_TRSM: case K_TRSM_CAST: return std::max(1, cdiv(d.m, trsm_rows(d.n)));
+    case K_TRSM: case K_TRSM_CAST: case K_TRTRI: case K_TRSM_INV:
+      return std::max(1, cdiv(d.m, trsm_rows(d.n)));
     case K_GEMM_RHS_N: case K_GEMM_RHS_T: return std::max(1, cdiv(d.m, RHS_ROWS));
     case K_CAST: case K_RESID: case K_AXPY:
       return std::max(1, cdiv(d.m, ROW_UNIT));
@@ -401,6 +405,29 @@ static int make_desc(dc_runtime *rt, dc_kind kind, const std::vector<Handle *> &
           return -EINVAL;
         d.d = S->ptr; d.ldd = S->ld;
       }
+      break;
+    }
+    case DC_TRTRI: {
+      Handle *L = H[0], *W = H[1];
+      if (!f64(L) || !f64(W)) return -EINVAL;
+      if (L->rows != L->cols || W->rows != L->rows || W->cols != L->rows || L->rows < 16 ||
+          L->rows > MAX_TILE)
+        return -EINVAL;
+      d.m = (int)L->rows; d.n = (int)L->rows;
+      d.a = L->ptr; d.lda = L->ld; d.ta = L->dtype;
+      d.c = W->ptr; d.ldc = W->ld; d.tc = W->dtype;
+      break;
+    }
+    case DC_TRSM_INV: {
+      Handle *L = H[0], *W = H[1], *X = H[2];
+      if (!f64(L) || !f64(W) || (X->dtype != DC_F64 && X->dtype != DC_F32)) return -EINVAL;
+      if (L->rows != L->cols || W->rows != L->rows || W->cols != L->rows ||
+          X->cols != L->rows || L->rows < 16 || L->rows > MAX_TILE)
+        return -EINVAL;
+      d.m = (int)X->rows; d.n = (int)L->rows;
+      d.a = W->ptr; d.lda = W->ld; d.ta = W->dtype;
+      d.b = L->ptr; d.ldb = L->ld; d.tb = L->dtype;
+      d.c = X->ptr; d.ldc = X->ld; d.tc = X->dtype;
       break;
     }
     case DC_SYRK: {
@@ -518,7 +545,7 @@ extern "C" int dc_task_submit(dc_runtime *rt, dc_kind kind, int nbuf, const dc_h
   if (rt->tasks.size() >= (size_t)INT32_MAX / 2) return -ENOMEM;
 
   // numerical-status slot: the root matrix of the factor this task touches
-  if (kind <= DC_GEMM_RHS_T || kind == DC_TRSM_CAST) {
+  if (kind <= DC_GEMM_RHS_T || kind == DC_TRSM_CAST || kind == DC_TRTRI || kind == DC_TRSM_INV) {
     const dc_handle root = rt->status_root_of(bufs[0]);
     auto it = rt->slot_of.find(root);
     int slot;
@@ -672,6 +699,8 @@ static void task_work(const TaskDesc &d, double *flops, double *bytes) {
     case K_POTRF: *flops = m * m * m / 3 + m * m / 2 + m / 6; *bytes = 2 * 8 * tri_m; break;
     case K_TRSM: *flops = m * n * n; *bytes = 8 * tri_n + 2 * esize(d.tc) * m * n; break;
     case K_TRSM_CAST: *flops = m * n * n; *bytes = 8 * tri_n + 2 * 4 * m * n + 2 * m * n; break;
+    case K_TRTRI: *flops = n * n * n / 3; *bytes = 2 * 8 * tri_n; break;
+    case K_TRSM_INV: *flops = m * n * n; *bytes = 8 * tri_n + 2 * esize(d.tc) * m * n; break;
     case K_SYRK: *flops = m * (m + 1) * k; *bytes = esize(d.ta) * m * k + 2 * esize(d.tc) * tri_m; break;
     case K_GEMM:
       *flops = 2 * m * n * k;
@@ -692,7 +721,8 @@ static void task_work(const TaskDesc &d, double *flops, double *bytes) {
 // LDS bytes the level kernel needs for a unit of this task.
 static size_t lds_for(const TaskDesc &d) {
   switch (d.kind) {
-    case K_TRSM: case K_TRSM_CAST: return (size_t)trsm_lds_doubles(d.n) * 8;
+    case K_TRSM: case K_TRSM_CAST: case K_TRTRI: case K_TRSM_INV:
+      return (size_t)trsm_lds_doubles(d.n) * 8;
     case K_POTRF: return (size_t)potrf_lds_doubles(d.m) * 8;
     case K_TRSM_L: case K_TRSM_LT: return (size_t)solve_lds_doubles(d.m) * 8;
     case K_GEMM_RHS_N: case K_GEMM_RHS_T: return (size_t)RHS_LDS_DOUBLES * 8;
@@ -708,6 +738,8 @@ static double cost_ns(const TaskDesc &d) {
     case K_GEMM: return 2.0 * m * n * k / (d.ta == T_F64 ? 200.0 : 400.0);
     case K_SYRK: return m * m * k / (d.ta == T_F64 ? 200.0 : 400.0);
     case K_TRSM: case K_TRSM_CAST: return m * n * n / 20.0;
+    case K_TRTRI: return n * n * n / 28.0;
+    case K_TRSM_INV: return m * n * n / 50.0;
     case K_POTRF: return m * m * m / 3.0 / 30.0 + 2000.0;
     case K_TRSM_L: case K_TRSM_LT: return m * m * 8.0 / 20.0 + 2000.0;
     case K_GEMM_RHS_N: case K_GEMM_RHS_T: return m * k * 8.0 / 50.0;
@@ -806,13 +838,22 @@ extern "C" int dc_flush(dc_runtime *rt) {
   std::vector<double> pcost(nl, 0.0), gcost(nl, 0.0);
   const bool timing = rt->ktiming;
   std::vector<double> wflops(timing ? 2 * nl : 0, 0.0), wbytes(timing ? 2 * nl : 0, 0.0);
+  // work items: one per unit, except FP64 GEMM/SYRK tasks, whose units are
+  // taken in pairs (units 2i and 2i + 1) by the two halves of a workgroup
+  auto paired = [&](const TaskDesc &d) { return is_gemm(d) && is_g64(d); };
+  auto items_of = [&](const TaskDesc &d) -> int64_t {
+    return paired(d) ? (d.nunits + 1) / 2 : d.nunits;
+  };
+  int64_t total_items = 0;
   for (int64_t t = 0; t < nt; ++t) {
     const TaskDesc &d = rt->tasks[t].desc;
+    const int64_t ni = items_of(d);
     total_units += d.nunits;
-    (is_gemm(d) ? gcount : pcount)[level[t]] += d.nunits;
-    if (is_gemm(d) && is_g64(d)) g64count[level[t]] += d.nunits;
+    total_items += ni;
+    (is_gemm(d) ? gcount : pcount)[level[t]] += ni;
+    if (paired(d)) g64count[level[t]] += ni;
     (is_gemm(d) ? gcost : pcost)[level[t]] += cost_ns(d);
-    lcount[level[t]] += d.nunits;
+    lcount[level[t]] += ni;
     if (timing) {
       double fl, by;
       task_work(d, &fl, &by);
@@ -827,7 +868,7 @@ extern "C" int dc_flush(dc_runtime *rt) {
   int64_t off = 0;
   auto take = [&](int64_t bytes) { int64_t o = off; off = align_up(off + bytes, 256); return o; };
   const int64_t o_desc = take(nt * (int64_t)sizeof(TaskDesc));
-  const int64_t o_items = take(total_units * 8);
+  const int64_t o_items = take(total_items * 8);
   const int64_t o_cnt = take(3 * nl * 8);
   const int64_t o_tail = off;
   const int64_t o_info = take(std::max(nslots_roots, 1) * 8);
@@ -877,7 +918,8 @@ extern "C" int dc_flush(dc_runtime *rt) {
     const bool g = is_gemm(k.desc);
     if (!g) llds[L] = std::max(llds[L], lds_for(k.desc));
     int64_t &fp = !g ? fillp[L] : is_g64(k.desc) ? fillg[L] : filll[L];
-    for (int u = 0; u < k.desc.nunits; ++u)
+    const int step = paired(k.desc) ? 2 : 1;
+    for (int u = 0; u < k.desc.nunits; u += step)
       items[fp++] = ((uint64_t)(uint32_t)t << 32) | (uint32_t)u;
   }
   memset(hb + o_cnt, 0, 3 * nl * 8);
@@ -928,13 +970,11 @@ extern "C" int dc_flush(dc_runtime *rt) {
       }
       pworkers = (int)std::min<int64_t>(pcount[L], (int64_t)pcus * std::max(1, per_cu));
     }
-    // CUs left to the GEMM kernels.  Next to the panel kernel, the FP64 GEMM
-    // kernel keeps to one workgroup per CU it is given, so that pcus CUs stay
-    // free for the panel kernel whichever kernel the hardware dispatches
-    // first (a panel workgroup needs a whole CU's registers); alone it runs
-    // two workgroups per CU.
+    // CUs left to the GEMM kernels.  Both take one workgroup per CU (a
+    // whole CU's LDS or registers), so launching gcus of them leaves pcus
+    // CUs free for the panel kernel, whichever kernel the hardware
+    // dispatches first (a panel workgroup also needs a whole CU).
     const int gcus = hasp ? std::max(1, cus - pcus) : cus;
-    const int g64_per_cu = hasp ? 1 : 2;
     int gworkers = 0;
     hipStream_t pstream = rt->stream;
     if (hasp && hasg) {
@@ -968,7 +1008,7 @@ extern "C" int dc_flush(dc_runtime *rt) {
         a.begin = gbegin[L];
         a.count = n64;
         a.counter = (unsigned long long *)(db + o_cnt) + 3 * L + 1;
-        const int wg = (int)std::min<int64_t>(n64, (int64_t)g64_per_cu * gcus);
+        const int wg = (int)std::min<int64_t>(n64, gcus);
         gworkers = std::max(gworkers, wg);
         int le = dcx_launch_gemm(a, wg, rt->stream);
         if (le != 0) { fail_hip((hipError_t)le, "gemm launch"); drop(); return -EIO; }

@@ -80,6 +80,8 @@ struct dc_runtime {
   std::vector<char> slot_factor;
 
   void *arena_dev = nullptr;
+  void *inv_ws = nullptr;                      // dc_potrf's inverse workspace
+  int64_t inv_ws_bytes = 0;
   void *arena_host = nullptr;
   int64_t arena_cap = 0;
   bool inflight = false;

@@ -112,6 +112,84 @@ def test_trsm_task(dc, rt, torch_dev, m, nb):
     assert np.abs(got - ref).max() <= 64 * nb * U * np.abs(ref).max() * np.linalg.cond(l)
 
 
+def _amp(l):
+    """max |L| * max |L^{-1}|: the error growth of a solve through the inverse."""
+    l = np.tril(l)
+    return np.abs(l).max() * np.abs(core.trtri_tile(l)).max()
+
+
+@pytest.mark.parametrize("nb", [16, 37, 128, 512])
+def test_trtri_task(dc, rt, torch_dev, nb):
+    l = np.linalg.cholesky(inputs.spd_uniform(nb, 7 * nb))
+    w0 = np.full((nb, nb), np.nan)
+    got = _single(dc, rt, dc.DC_TRTRI, [l, w0], [dc.DC_R, dc.DC_W], torch_dev)[1]
+    ref = core.trtri_tile(l)
+    lo = np.tril_indices(nb)
+    assert np.abs(got[lo] - ref[lo]).max() <= 64 * nb * U * np.abs(ref).max() * np.linalg.cond(l)
+    # the strictly upper part holds the two kinds of slots and nothing else
+    nb16 = (nb + 15) // 16
+    wl = np.tril(got)
+    for u in range(nb16):
+        assert got[0, 1 + u] == np.abs(wl[:, 16 * u:16 * u + 16]).max()
+    assert got[1, 2] == np.abs(np.tril(l)).max()
+    up = np.triu(np.ones((nb, nb), bool), 1)
+    up[0, 1:1 + nb16] = False
+    up[1, 2] = False
+    assert np.all(np.isnan(got[up]))
+
+
+@pytest.mark.parametrize("m,nb,x32", [(128, 128, False), (100, 37, False), (512, 512, False),
+                                      (33, 256, False), (77, 512, True), (16, 16, False)])
+def test_trsm_inv_task(dc, rt, torch_dev, m, nb, x32):
+    g = np.random.default_rng(m + nb)
+    l = np.linalg.cholesky(inputs.spd_uniform(nb, nb))
+    assert _amp(l) <= 1024   # the inverse product path, not the fallback
+    x = g.standard_normal((m, nb))
+    if x32:
+        x = x.astype(np.float32)
+    torch, dev = torch_dev
+    tl, tx = _gpu(torch_dev, l), _gpu(torch_dev, x)
+    tw = torch.zeros((nb, nb), dtype=torch.float64, device=dev)
+    hl, hw, hx = rt.register_tensor(tl), rt.register_tensor(tw), rt.register_tensor(tx)
+    rt.dc_task_submit(dc.DC_TRTRI, [hl, hw], [dc.DC_R, dc.DC_W])
+    rt.dc_task_submit(dc.DC_TRSM_INV, [hl, hw, hx], [dc.DC_R, dc.DC_R, dc.DC_RW])
+    rt.dc_wait_all()
+    for h in (hl, hw, hx):
+        rt.dc_unregister(h)
+    got = tx.cpu().numpy().astype(np.float64)
+    ref = core.trsm_inv_tile(core.trtri_tile(l), x.astype(np.float64))
+    tol = 64 * nb * U * np.abs(ref).max() * np.linalg.cond(l)
+    if x32:
+        tol += 2.0 ** -24 * np.abs(ref).max()
+    assert np.abs(got - ref).max() <= tol
+    # the same operation as the substitution (different rounding)
+    sub = core.trsm_tile(l, x.astype(np.float64))
+    assert np.abs(got - sub).max() <= tol + 64 * nb * U * np.abs(sub).max() * np.linalg.cond(l)
+
+
+@pytest.mark.parametrize("m,nb", [(64, 64), (40, 100)])
+def test_trsm_inv_falls_back_to_substitution(dc, rt, torch_dev, m, nb):
+    # integer L with entries up to 3 and power-of-two diagonal: its inverse
+    # grows like 4^nb, far past the limit, so TRSM_INV must solve by
+    # substitution and give the TRSM task's bits
+    _, l0 = inputs.integer_factor(nb, 11)
+    assert _amp(l0) > 1024
+    g = np.random.default_rng(m * nb)
+    x = (g.integers(-3, 4, (m, nb)).astype(np.float64)) @ l0.T
+    torch, dev = torch_dev
+    tl, tx = _gpu(torch_dev, l0), _gpu(torch_dev, x)
+    tw = torch.zeros((nb, nb), dtype=torch.float64, device=dev)
+    hl, hw, hx = rt.register_tensor(tl), rt.register_tensor(tw), rt.register_tensor(tx)
+    rt.dc_task_submit(dc.DC_TRTRI, [hl, hw], [dc.DC_R, dc.DC_W])
+    rt.dc_task_submit(dc.DC_TRSM_INV, [hl, hw, hx], [dc.DC_R, dc.DC_R, dc.DC_RW])
+    rt.dc_wait_all()
+    for h in (hl, hw, hx):
+        rt.dc_unregister(h)
+    sub = _single(dc, rt, dc.DC_TRSM, [l0, x], [dc.DC_R, dc.DC_RW], torch_dev)[1]
+    assert np.array_equal(tx.cpu().numpy(), sub)
+    assert np.array_equal(sub, core.trsm_tile(l0, x))
+
+
 @pytest.mark.parametrize("nb", [1, 16, 37, 128, 512])
 def test_potrf_task(dc, rt, torch_dev, nb):
     a = inputs.spd_normal(nb, nb, 0.1)

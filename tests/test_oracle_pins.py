@@ -59,6 +59,68 @@ def test_trsm_tile_matches_scipy(m, nb):
     assert np.allclose(got @ l.T, x, atol=64 * nb * U * np.abs(x).max())
 
 
+def test_trtri_bidiagonal_closed_form():
+    # L = I - s * subdiagonal has the inverse W_ij = s^(i-j) (i >= j); with
+    # s = 1/2 every entry and every partial sum is exact
+    n, s = 12, 0.5
+    l = np.eye(n) - s * np.eye(n, k=-1)
+    ref = np.tril(np.fromfunction(lambda i, j: s ** (i - j), (n, n)))
+    assert np.array_equal(core.trtri_tile(l), ref)
+
+
+def test_trtri_diagonal_and_upper_zero():
+    d = np.array([1.0, 2.0, 0.25, 8.0, 4.0])
+    w = core.trtri_tile(np.diag(d))
+    assert np.array_equal(w, np.diag(1.0 / d))
+
+
+def test_trtri_integer_unit_lower_is_exact_inverse():
+    # an integer unit lower-triangular matrix has an integer inverse; small
+    # entries keep every partial sum exact
+    g = np.random.default_rng(5)
+    n = 10
+    l = np.tril(g.integers(-1, 2, (n, n)).astype(np.float64), -1) + np.eye(n)
+    w = core.trtri_tile(l)
+    assert np.array_equal(w, np.round(w))
+    assert np.array_equal(w @ l, np.eye(n))
+    assert np.array_equal(l @ w, np.eye(n))
+
+
+@pytest.mark.parametrize("nb", [1, 7, 48])
+def test_trtri_matches_scipy(nb):
+    l = np.linalg.cholesky(inputs.spd_uniform(nb, 3 * nb))
+    w = core.trtri_tile(l)
+    ref = sla.solve_triangular(l, np.eye(nb), lower=True)
+    assert np.abs(w - ref).max() <= 64 * nb * U * np.abs(ref).max() * np.linalg.cond(l)
+    assert np.abs(w @ l - np.eye(nb)).max() <= 64 * nb * U * np.linalg.cond(l)
+
+
+@pytest.mark.parametrize("m,nb", [(1, 1), (6, 9), (40, 32)])
+def test_trsm_inv_tile_is_product_with_inverse(m, nb):
+    g = np.random.default_rng(m + 7 * nb)
+    l = np.linalg.cholesky(inputs.spd_uniform(nb, nb))
+    x = g.standard_normal((m, nb))
+    w = core.trtri_tile(l)
+    got = core.trsm_inv_tile(w, x)
+    assert np.allclose(got, x @ w.T, rtol=0, atol=4 * nb * U * (np.abs(x) @ np.abs(w).T).max())
+    # the same operation as the substitution TRSM
+    ref = core.trsm_tile(l, x)
+    assert np.abs(got - ref).max() <= 64 * nb * U * np.abs(ref).max() * np.linalg.cond(l)
+    # only the lower part of W is read
+    wn = w.copy()
+    wn[np.triu_indices(nb, 1)] = np.nan
+    assert np.array_equal(core.trsm_inv_tile(wn, x), got)
+
+
+def test_trsm_inv_tile_exact_on_dyadic_case():
+    n, s = 8, 0.5
+    l = np.eye(n) - s * np.eye(n, k=-1)
+    x = np.random.default_rng(2).integers(-4, 5, (5, n)).astype(np.float64)
+    got = core.trsm_inv_tile(core.trtri_tile(l), x)
+    assert np.array_equal(got, core.trsm_tile(l, x))
+    assert np.array_equal(got @ l.T, x)
+
+
 @pytest.mark.parametrize("m,nn,kb", [(1, 1, 1), (7, 5, 3), (33, 17, 64)])
 def test_gemm_tile_matches_numpy(m, nn, kb):
     g = np.random.default_rng(m + 7 * nn + 31 * kb)
