@@ -11,8 +11,10 @@ step, outside the timed region.
 Each step is one dc_potrf call (graph build, upload, all level launches,
 wait), timed with HIP events on the stream the library launches on.  The
 JSON line reports GFLOP/s from the LAPACK flop count n^3/3 + n^2/2 + n/6,
-the roofline of the level kernel against the FP64 MFMA peak, and the CPU
-oracle timed on a bounded sample on the host cores.
+the roofline of the GEMM/SYRK kernel against the FP64 MFMA peak (its HBM
+traffic per launch from the committed rocprofv3 counter summary while the
+kernel source is unchanged), and the CPU oracle timed on a bounded sample on
+the host cores.
 """
 import argparse
 import json
@@ -27,6 +29,25 @@ sys.path.insert(0, ROOT)
 FP64_PEAK_TFLOPS = 78.6   # MI355X dense FP64 matrix peak (published)
 FP32_PEAK_TFLOPS = 157.3  # MI355X dense FP32 matrix peak (published)
 METRIC = "Cholesky GFLOP/s + % MFMA peak (FP64 vs mixed@1e-10); solves/s with p50/p99"
+PROFILE = os.path.join(ROOT, "profiles", "dc_gemm_kernel_fp64_n32768.md")
+
+
+def stored_traffic(n, tile):
+    """HBM bytes per launch of the GEMM kernel from the committed rocprofv3
+    counter summary, or None when it does not apply: another workload, or a
+    kernel source that changed since the counters were taken (SHA-256)."""
+    import hashlib
+    if (n, tile) != (32768, 512) or not os.path.exists(PROFILE):
+        return None
+    for line in open(PROFILE):
+        if line.startswith("traffic: "):
+            rec = json.loads(line[len("traffic: "):])
+            src = os.path.join(ROOT, rec["source"])
+            with open(src, "rb") as f:
+                if hashlib.sha256(f.read()).hexdigest() != rec["source_sha256"]:
+                    return None
+            return rec["bytes_per_launch"]
+    return None
 
 
 def flops_potrf(n):
@@ -368,10 +389,11 @@ def main():
                    "host_graph_build_ms": round(sum(builds) / len(builds), 3)},
         "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
-                     "traffic": None, "kernel": "dc_gemm_kernel",
+                     "traffic": stored_traffic(n, tile), "kernel": "dc_gemm_kernel",
                      "launches_per_step": gk["launches"] / args.steps,
                      "avg_launch_us": round(gk["ms"] / gk["launches"] * 1e3, 2),
-                     "flops_per_launch": gk["flops"] / gk["launches"]},
+                     "flops_per_launch": gk["flops"] / gk["launches"],
+                     "algorithmic_bytes_per_launch": gk["bytes"] / gk["launches"]},
         "pct_fp64_mfma_peak_whole_factor": round(100 * gflops / 1e3 / FP64_PEAK_TFLOPS, 2),
         "panel_kernel": {"kernel": "dc_level_kernel", "launches_per_step": pk["launches"] / args.steps,
                          "avg_launch_us": round(pk["ms"] / max(pk["launches"], 1) * 1e3, 2),

@@ -105,6 +105,13 @@ typedef enum { DC_F64 = 0, DC_F32 = 1, DC_BF16 = 2 } dc_dtype;
  *                                   inverse would lose accuracy) it solves
  *                                   with L by substitution like DC_TRSM.
  *                                   X FP64 or FP32.
+ *   DC_TRSM_INV_CAST (L:R, W:R, X:RW, S:W)  TRSM_INV on an FP32 tile X that
+ *                                   also writes S = BF16(X).
+ *   DC_TRSM_L_INV  (L:R, W:R, B:RW) B <- L^{-1} B computed as W B, and
+ *   DC_TRSM_LT_INV (L:R, W:R, B:RW) B <- L^{-T} B computed as W^T B, with W
+ *                                   from DC_TRTRI of the same L (FP64 L, W
+ *                                   and B, order 16..512); both fall back to
+ *                                   substitution like DC_TRSM_INV.
  * Precisions (the dtypes of the handles select the kernel):
  *   POTRF: FP64.  TRSM: L FP64, X FP64 or FP32 (FP64 arithmetic, FP32 tiles
  *   rounded on store).  SYRK/GEMM: FP64 inputs update FP64 tiles with FP64
@@ -116,8 +123,9 @@ typedef enum {
   DC_POTRF = 0, DC_TRSM = 1, DC_SYRK = 2, DC_GEMM = 3,
   DC_TRSM_L = 4, DC_GEMM_RHS_N = 5, DC_TRSM_LT = 6, DC_GEMM_RHS_T = 7,
   DC_SCAL = 8, DC_CAST = 9, DC_RESID = 10, DC_AXPY = 11, DC_TRSM_CAST = 12,
-  DC_TRTRI = 13, DC_TRSM_INV = 14,
-  DC_NUM_KINDS = 15
+  DC_TRTRI = 13, DC_TRSM_INV = 14, DC_TRSM_INV_CAST = 15,
+  DC_TRSM_L_INV = 16, DC_TRSM_LT_INV = 17,
+  DC_NUM_KINDS = 18
 } dc_kind;
 
 typedef struct {

@@ -36,6 +36,12 @@
  * operation; it never changes the operation sequence of any element, so
  * results do not depend on the thread count.
  *
+ * The panel solve may also be taken through the inverse of the diagonal
+ * factor: or_trtri_tile forms W = L^{-1} by forward substitution on the
+ * columns of the identity, or_trsm_inv_tile applies X <- X W^T.  Both are the
+ * plain definitions of those operations; the tiled factor above always uses
+ * the substitution (or_trsm_tile).
+ *
  * Checkers accumulate in x87 80-bit long double.
  */
 #include <math.h>

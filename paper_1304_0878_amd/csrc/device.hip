@@ -46,6 +46,7 @@ typedef __attribute__((address_space(1))) double gdouble;
 typedef double dvec2 __attribute__((ext_vector_type(2)));
 typedef __attribute__((address_space(1))) dvec2 gdvec2;
 typedef __attribute__((address_space(1))) float gfloat;
+typedef __attribute__((address_space(1))) __bf16 gbf16;
 template <typename T> using gptr = __attribute__((address_space(1))) T *;
 
 __device__ __forceinline__ double mfma44(double a, double b, double c) {
@@ -226,7 +227,6 @@ __device__ __forceinline__ void trsm_core(const TaskDesc &d, int unit, double *l
     }
     return;
   }
-  typedef __attribute__((address_space(1))) __bf16 gbf16;
   gbf16 *S16 = d.d ? (gbf16 *)d.d + (int64_t)r0 * d.ldd : nullptr;
   for (int idx = tid; idx < rows * nb; idx += NT) {
     const int r = idx / nb, c = idx - r * nb;
@@ -264,22 +264,41 @@ __device__ __forceinline__ void run_trsm(const TaskDesc &d, int unit, double *ld
 // accuracy.
 constexpr double INV_LIMIT = 1024.0;
 
-template <bool FULL>
+// The product, shared with the diagonal steps of the solves (MODE):
+//   INV_PANEL  X (m x nb) rows r0.. <- X W^T          (TRSM_INV, W = L^{-1})
+//   INV_FWD    B (nb x r) cols c0.. <- W B = L^{-1} B  (TRSM_L_INV)
+//   INV_BWD    B (nb x r) cols c0.. <- W^T B = L^{-T} B (TRSM_LT_INV)
+// In the solve modes the unit's 16 right-hand-side columns are staged as
+// the 16 rows of X (X = B^T), so out[c][i] = sum_k X[c][k] Wop[i][k] with
+// Wop = W (forward, k <= i) or W^T (backward, k >= i).  Backward reads W
+// by rows k, 16 lanes taking 16 consecutive columns i.
+constexpr int INV_PANEL = 0, INV_FWD = 1, INV_BWD = 2;
+
+template <bool FULL, int MODE>
 __device__ __forceinline__ void trsm_inv_product(const TaskDesc &d, int unit, double *lds) {
-  const int nb = d.n;
+  const bool solve = MODE != INV_PANEL;
+  const int nb = solve ? d.m : d.n;
   const int nb16 = (nb + 15) / 16;
   const int r0 = unit * TRSM_ROWS;
-  const int rows = min(TRSM_ROWS, d.m - r0);
+  // X rows: rows of X (panel), or right-hand-side columns (solves)
+  const int rows = min(TRSM_ROWS, (solve ? d.n : d.m) - r0);
   const int XS = panel_stride(nb);
   const gdouble *W = (const gdouble *)d.a;
   const int64_t ldw = d.lda;
   const int64_t ldc = d.ldc;
-  const bool x32 = d.tc == T_F32;
+  const bool x32 = !solve && d.tc == T_F32;
   double *Xs = lds;
-  if (x32)
+  if (solve) {
+    const gdouble *Bm = (const gdouble *)d.c;
+    for (int idx = threadIdx.x; idx < TRSM_ROWS * nb; idx += NT) {
+      const int k = idx >> 4, c = idx & 15;
+      Xs[c * XS + k] = c < rows ? Bm[(int64_t)k * ldc + r0 + c] : 0.0;
+    }
+  } else if (x32) {
     stage16<float>(Xs, XS, (gfloat *)d.c + (int64_t)r0 * ldc, ldc, rows, nb);
-  else
+  } else {
     stage16<double>(Xs, XS, (gdouble *)d.c + (int64_t)r0 * ldc, ldc, rows, nb);
+  }
   __syncthreads();
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int l16 = lane & 15, kq = lane >> 4;
@@ -287,27 +306,33 @@ __device__ __forceinline__ void trsm_inv_product(const TaskDesc &d, int unit, do
   dvec4 acc[8];
 #pragma unroll
   for (int i = 0; i < 8; ++i) acc[i] = dvec4{0.0, 0.0, 0.0, 0.0};
-  // B operand of block b, chunk kc: W[16b + l16][16kc + 4kq + s], s < 4
+  // block b takes chunk kc when the chunk meets the triangle of Wop
+  auto active = [&](int b, int kc) { return b < nb16 && (MODE == INV_BWD ? b <= kc : b >= kc); };
+  // B operand of block b, chunk kc, step s: Wop[16b + l16][16kc + 4kq + s]
   auto wload = [&](int kc, double (&v)[8][4]) {
     const int k = 16 * kc + 4 * kq;
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
       const int b = w + 4 * i;
-      if (b >= kc && b < nb16) {
-        const int row = 16 * b + l16;
-        if (FULL) {
-          const gdvec2 *p = (const gdvec2 *)(W + (int64_t)row * ldw + k);
+      if (active(b, kc)) {
+        const int col = 16 * b + l16;   // output column i
+        if (MODE == INV_BWD) {
+#pragma unroll
+          for (int s = 0; s < 4; ++s)
+            v[i][s] = (FULL || (col < nb && k + s < nb)) ? W[(int64_t)(k + s) * ldw + col] : 0.0;
+        } else if (FULL) {
+          const gdvec2 *p = (const gdvec2 *)(W + (int64_t)col * ldw + k);
           const dvec2 x0 = p[0], x1 = p[1];
           v[i][0] = x0[0]; v[i][1] = x0[1]; v[i][2] = x1[0]; v[i][3] = x1[1];
         } else {
 #pragma unroll
           for (int s = 0; s < 4; ++s)
-            v[i][s] = (row < nb && k + s < nb) ? W[(int64_t)row * ldw + k + s] : 0.0;
+            v[i][s] = (col < nb && k + s < nb) ? W[(int64_t)col * ldw + k + s] : 0.0;
         }
-        if (b == kc) {   // diagonal chunk: only k <= row is part of W
+        if (b == kc) {   // diagonal chunk: only the triangle of W is read
 #pragma unroll
           for (int s = 0; s < 4; ++s)
-            if (4 * kq + s > l16) v[i][s] = 0.0;
+            if (MODE == INV_BWD ? 4 * kq + s < l16 : 4 * kq + s > l16) v[i][s] = 0.0;
         }
       }
     }
@@ -320,7 +345,7 @@ __device__ __forceinline__ void trsm_inv_product(const TaskDesc &d, int unit, do
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
       const int b = w + 4 * i;
-      if (b >= kc && b < nb16) {
+      if (active(b, kc)) {
 #pragma unroll
         for (int s = 0; s < 4; ++s)
           acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], v[i][s], acc[i], 0, 0, 0);
@@ -347,32 +372,43 @@ __device__ __forceinline__ void trsm_inv_product(const TaskDesc &d, int unit, do
       for (int e = 0; e < 4; ++e) {
         const int row = kq + 4 * e;
         if (row < rows) {
-          if (x32)
-            ((gfloat *)d.c)[(int64_t)(r0 + row) * ldc + col] = (float)acc[i][e];
-          else
+          if (solve) {
+            ((gdouble *)d.c)[(int64_t)col * ldc + r0 + row] = acc[i][e];
+          } else if (x32) {
+            const float v = (float)acc[i][e];
+            ((gfloat *)d.c)[(int64_t)(r0 + row) * ldc + col] = v;
+            if (d.d) ((gbf16 *)d.d)[(int64_t)(r0 + row) * d.ldd + col] = (__bf16)v;
+          } else {
             ((gdouble *)d.c)[(int64_t)(r0 + row) * ldc + col] = acc[i][e];
+          }
         }
       }
     }
   }
 }
 
-__device__ __forceinline__ void run_trsm_inv(const TaskDesc &d, int unit, double *lds) {
-  const int nb = d.n;
+// Whether a task through W may use the inverse: max|L| * max|W| from the
+// slots TRTRI wrote into W's strictly upper part.
+__device__ __forceinline__ bool inverse_usable(const TaskDesc &d, int nb) {
   const int nb16 = (nb + 15) / 16;
   const gdouble *W = (const gdouble *)d.a;
   double wmax = 0.0;
   for (int u = 0; u < nb16; ++u) wmax = fmax(wmax, W[(int64_t)INV_SLOT_ROW_W * d.lda + 1 + u]);
   const double lmax = W[(int64_t)INV_SLOT_L * d.lda + 2];
-  const double amp = wmax * lmax;
-  const int use_inverse = __builtin_amdgcn_readfirstlane(amp <= INV_LIMIT ? 1 : 0);
-  if (!use_inverse) {
+  return __builtin_amdgcn_readfirstlane(wmax * lmax <= INV_LIMIT ? 1 : 0) != 0;
+}
+
+__device__ __forceinline__ bool inverse_full(const TaskDesc &d, int nb) {
+  return nb % 16 == 0 && d.lda % 2 == 0 && ((uintptr_t)d.a & 15) == 0;
+}
+
+__device__ __forceinline__ void run_trsm_inv(const TaskDesc &d, int unit, double *lds) {
+  if (!inverse_usable(d, d.n))
     trsm_core<false>(d, unit, lds, (const gdouble *)d.b, d.ldb);
-  } else if (nb % 16 == 0 && d.lda % 2 == 0 && ((uintptr_t)d.a & 15) == 0) {
-    trsm_inv_product<true>(d, unit, lds);
-  } else {
-    trsm_inv_product<false>(d, unit, lds);
-  }
+  else if (inverse_full(d, d.n))
+    trsm_inv_product<true, INV_PANEL>(d, unit, lds);
+  else
+    trsm_inv_product<false, INV_PANEL>(d, unit, lds);
 }
 
 // ----------------------------------------------------------------- POTRF
@@ -778,6 +814,28 @@ __device__ __forceinline__ void run_trsm_lt(const TaskDesc &d, double *lds) {
   }
 }
 
+// Diagonal step of a solve through W = L^{-1} (TRSM_L_INV, TRSM_LT_INV):
+// unit u takes right-hand-side columns 16u..16u+15.  With an ill-conditioned
+// L (see TRSM_INV) unit 0 solves all columns by substitution with L and the
+// other units do nothing.
+template <int MODE>
+__device__ __forceinline__ void run_trsm_l_inv(const TaskDesc &d, int unit, double *lds) {
+  if (!inverse_usable(d, d.m)) {
+    if (unit == 0) {
+      TaskDesc dd = d;
+      dd.a = d.b;
+      dd.lda = d.ldb;
+      dd.ta = T_F64;
+      if (MODE == INV_FWD) run_trsm_l<double>(dd, lds); else run_trsm_lt<double>(dd, lds);
+    }
+    return;
+  }
+  if (inverse_full(d, d.m))
+    trsm_inv_product<true, MODE>(d, unit, lds);
+  else
+    trsm_inv_product<false, MODE>(d, unit, lds);
+}
+
 // B_I (m x r) -= L_IK (m x kb) Y_K (kb x r); unit = 16 rows, thread (row,
 // slice) sums every 16th term with eight loads in flight; fixed-order
 // reduction over the slices in LDS.
@@ -1099,7 +1157,9 @@ __global__ void __launch_bounds__(NT, 1) dc_level_kernel(LevelArgs A) {
       switch (kind) {
         case K_TRSM: case K_TRSM_CAST: run_trsm(d, u, lds); break;
         case K_TRTRI: trsm_core<true>(d, u, lds, (const gdouble *)d.a, d.lda); break;
-        case K_TRSM_INV: run_trsm_inv(d, u, lds); break;
+        case K_TRSM_INV: case K_TRSM_INV_CAST: run_trsm_inv(d, u, lds); break;
+        case K_TRSM_L_INV: run_trsm_l_inv<INV_FWD>(d, u, lds); break;
+        case K_TRSM_LT_INV: run_trsm_l_inv<INV_BWD>(d, u, lds); break;
         case K_POTRF: {
           const int bad = run_potrf(d, lds);
           if (bad && tid == 0 && d.matrix >= 0) {

@@ -11,8 +11,8 @@ enum Kind : int32_t {
   K_POTRF = 0, K_TRSM = 1, K_SYRK = 2, K_GEMM = 3,
   K_TRSM_L = 4, K_GEMM_RHS_N = 5, K_TRSM_LT = 6, K_GEMM_RHS_T = 7,
   K_SCAL = 8, K_CAST = 9, K_RESID = 10, K_AXPY = 11, K_TRSM_CAST = 12,
-  K_TRTRI = 13, K_TRSM_INV = 14,
-  K_NUM = 15
+  K_TRTRI = 13, K_TRSM_INV = 14, K_TRSM_INV_CAST = 15, K_TRSM_L_INV = 16, K_TRSM_LT_INV = 17,
+  K_NUM = 18
 };
 
 enum DType : int32_t { T_F64 = 0, T_F32 = 1, T_BF16 = 2 };
@@ -93,9 +93,10 @@ extern "C++" int dcx_launch_level(const dcx::LevelArgs &args, int workers, size_
                                   void *stream);
 // Allows the level kernel its largest dynamic LDS size.
 extern "C++" int dcx_level_setup(void);
-// Launches the FP64 GEMM/SYRK kernel of one level on `stream`.
-extern "C++" int dcx_launch_gemm(const dcx::LevelArgs &args, int workers, void *stream);
-// Launches the GEMM/SYRK kernel for FP32/BF16 inputs of one level on `stream`.
+// Launches the GEMM/SYRK kernel for inputs of dtype ta (T_F64 or T_F32) of
+// one level on `stream` (work items are pairs of units).
+extern "C++" int dcx_launch_gemm(const dcx::LevelArgs &args, int workers, int ta, void *stream);
+// Launches the GEMM/SYRK kernel for BF16 inputs of one level on `stream`.
 extern "C++" int dcx_launch_gemm_lowp(const dcx::LevelArgs &args, int workers, void *stream);
 // Allows the GEMM/SYRK kernels their dynamic LDS sizes.
 extern "C++" int dcx_gemm_setup(void);

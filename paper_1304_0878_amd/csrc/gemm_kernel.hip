@@ -74,8 +74,9 @@ __device__ __forceinline__ uint64_t uniform_u64(uint64_t v) {
 
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t span_rsrc(const void *base, int64_t rows,
-                                                            int64_t ld, int64_t cols) {
-  const int64_t bytes = rows > 0 ? ((rows - 1) * ld + cols) * 8 : 0;
+                                                            int64_t ld, int64_t cols,
+                                                            int esize = 8) {
+  const int64_t bytes = rows > 0 ? ((rows - 1) * ld + cols) * esize : 0;
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), 0, (int)(uint32_t)bytes,
                                            0x00020000);
 }
@@ -85,6 +86,17 @@ __device__ __forceinline__ double bload(__amdgpu_buffer_rsrc_t r, uint32_t voff,
 __device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff,
                                        double v) {
   __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, 0);
+}
+typedef float fvec2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ float bloadf(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+__device__ __forceinline__ fvec2 bloadf2(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  return __builtin_bit_cast(fvec2, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+__device__ __forceinline__ void bstoref(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff,
+                                        float v) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, voff, soff, 0);
 }
 
 // Ragged units (M or N below the unit size, K not a multiple of the chunk)
@@ -198,9 +210,124 @@ __device__ __forceinline__ void block_f64(void *C, int64_t ldc, const void *A, i
       }
 }
 
-// ------------------------------------------------- FP32 and BF16 inputs
+// FP32 inputs in the same two-half workgroup: the FP64 block's structure
+// with 16x16x4 FP32 MFMA (result element e of lane l is D[4(l/16) + e][l%16]),
+// K chunks of 32 floats in LDS with a row stride of 34 floats (the 32 lanes
+// of one half-wave read 16 rows at two adjacent columns: banks 2*row + kq are
+// distinct), two floats per lane and row in each global load, FP32
+// accumulation, and C <- C - acc in C's own precision at the end (an FP64
+// tile keeps its FP64 value; only the product is FP32).
+constexpr int KCF = 32;
+constexpr int SF = KCF + 2;                   // floats per LDS row
+constexpr int STAGEF = 2 * GEMM_UNIT * SF;    // A and B of one stage
+static_assert(2 * STAGEF * 4 <= 2 * STAGE64 * 8, "FP32 stages fit a half's LDS");
 
-// Epilogue shared by the low-precision paths: 16x16 MFMA output layout
+template <bool FULL, typename TOUT>
+__device__ __forceinline__ void block_f32p(void *C, int64_t ldc, const void *A, int64_t lda,
+                                           const void *B, int64_t ldb, int M, int N, int K,
+                                           int dlim, float *lds, int tid) {
+  const int lane = tid & 63, w = tid >> 6;
+  const int wr = w >> 1, wc = w & 1;
+  const int l16 = lane & 15, kq = lane >> 4;
+  const __amdgpu_buffer_rsrc_t rc = span_rsrc(C, M, ldc, N, (int)sizeof(TOUT));
+  const __amdgpu_buffer_rsrc_t ra_ = span_rsrc(A, M, lda, K, 4);
+  const __amdgpu_buffer_rsrc_t rb_ = span_rsrc(B, N, ldb, K, 4);
+  fvec4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = (fvec4){0.f, 0.f, 0.f, 0.f};
+  // loader: thread -> rows tid/16 + 16 jj, columns 2(tid%16), +1 of the chunk
+  const int lrow = tid >> 4, lcol = (tid & 15) * 2;
+  const uint32_t ald = (uint32_t)lda * 4, bld = (uint32_t)ldb * 4;
+  const uint32_t av = (uint32_t)lrow * ald + lcol * 4, bv = (uint32_t)lrow * bld + lcol * 4;
+  fvec2 ra[8], rb[8];
+  auto gload = [&](int k0) {
+    if (FULL) {
+#pragma unroll
+      for (int jj = 0; jj < 8; ++jj) {
+        ra[jj] = bloadf2(ra_, av, 16 * jj * ald + k0 * 4);
+        rb[jj] = bloadf2(rb_, bv, 16 * jj * bld + k0 * 4);
+      }
+    } else {
+#pragma unroll
+      for (int jj = 0; jj < 8; ++jj) {
+        const uint32_t ar = min(lrow + 16 * jj, M - 1), br = min(lrow + 16 * jj, N - 1);
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+          const int k = k0 + lcol + e;
+          const uint32_t kc = min(k, K - 1);
+          const float x = bloadf(ra_, (ar * (uint32_t)lda + kc) * 4, 0);
+          const float y = bloadf(rb_, (br * (uint32_t)ldb + kc) * 4, 0);
+          ra[jj][e] = k < K ? x : 0.f;
+          rb[jj][e] = k < K ? y : 0.f;
+        }
+      }
+    }
+  };
+  auto sstore = [&](int st) {
+    float *As = lds + st * STAGEF;
+    float *Bs = As + GEMM_UNIT * SF;
+#pragma unroll
+    for (int jj = 0; jj < 8; ++jj) {
+      *(fvec2 *)(As + (lrow + 16 * jj) * SF + lcol) = ra[jj];
+      *(fvec2 *)(Bs + (lrow + 16 * jj) * SF + lcol) = rb[jj];
+    }
+  };
+  const int nst = (K + KCF - 1) / KCF;
+  gload(0);
+  sstore(0);
+  __syncthreads();
+  for (int st = 0; st < nst; ++st) {
+    const int cur = st & 1;
+    if (st + 1 < nst) gload((st + 1) * KCF);
+    const float *As = lds + cur * STAGEF;
+    const float *Bs = As + GEMM_UNIT * SF;
+#pragma unroll
+    for (int ks = 0; ks < KCF / 4; ++ks) {
+      const int kk = 4 * ks + kq;
+      float a[4], b[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = As[(64 * wr + 16 * i + l16) * SF + kk];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) b[j] = Bs[(64 * wc + 16 * j + l16) * SF + kk];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    if (st + 1 < nst) sstore(cur ^ 1);
+    __syncthreads();
+  }
+  const int r0 = 64 * wr + 4 * kq, c0 = 64 * wc + l16;   // element (i, j, e) at r0 + 16i + e, c0 + 16j
+  const int dbase = c0 - r0;
+  constexpr uint32_t es = sizeof(TOUT);
+  const uint32_t cld = (uint32_t)ldc * es;
+  const uint32_t cv = ((uint32_t)r0 * (uint32_t)ldc + c0) * es;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int row = r0 + 16 * i + e, col = c0 + 16 * j;
+        if ((FULL || (row < M && col < N)) && dbase + 16 * (j - i) - e <= dlim) {
+          const uint32_t so = (16 * i + e) * cld;
+          if (sizeof(TOUT) == 8) {
+            const double v = bload(rc, cv + 16 * es * j, so);
+            bstore(rc, cv + 16 * es * j, so, v - (double)acc[i][j][e]);
+          } else {
+            const float v = bloadf(rc, cv + 16 * es * j, so);
+            bstoref(rc, cv + 16 * es * j, so, v - acc[i][j][e]);
+          }
+        }
+      }
+}
+
+// ------------------------------------------------------------ BF16 inputs
+
+// Epilogue of the BF16 path: 16x16 MFMA output layout
 // (lane l holds rows 4(l/16)+e, column l%16 of its 16x16 tile).
 template <typename TOUT>
 __device__ __forceinline__ void store_lowp(gp<TOUT> __restrict__ C, int64_t ldc, int M, int N,
@@ -221,83 +348,6 @@ __device__ __forceinline__ void store_lowp(gp<TOUT> __restrict__ C, int64_t ldc,
           *p = *p - (TOUT)acc[i][c][e];
         }
       }
-}
-
-constexpr int KC32 = 32;
-constexpr int S32 = KC32 + 4;                 // floats per LDS row
-constexpr int STAGE32 = 2 * GEMM_UNIT * S32;
-
-template <typename TOUT>
-__device__ __forceinline__ void block_f32(gp<TOUT> __restrict__ C, int64_t ldc,
-                                          const gfloat *__restrict__ A, int64_t lda,
-                                          const gfloat *__restrict__ B, int64_t ldb, int M,
-                                          int N, int K, bool lower_only, float *lds) {
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int wr = w >> 2, wc = w & 3;
-  const int l16 = lane & 15, kq = lane >> 4;
-  fvec4 acc[4][2];
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int c = 0; c < 2; ++c) acc[i][c] = (fvec4){0.f, 0.f, 0.f, 0.f};
-  // loader: 8 threads per row (four floats each), 64 rows per pass, 2 passes
-  const int lrow = tid >> 3, lk = (tid & 7) * 4;
-  const bool fast = M == GEMM_UNIT && N == GEMM_UNIT && (K % KC32) == 0 &&
-                    (((uintptr_t)A | (uintptr_t)B) & 15) == 0 && ((lda | ldb) & 3) == 0;
-  fvec4 ra[2], rb[2];
-  auto gload = [&](int k0) {
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const int row = lrow + 64 * j;
-      if (fast) {
-        ra[j] = *(const gfvec4 *)(A + (int64_t)row * lda + k0 + lk);
-        rb[j] = *(const gfvec4 *)(B + (int64_t)row * ldb + k0 + lk);
-      } else {
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int k = k0 + lk + e;
-          ra[j][e] = (row < M && k < K) ? A[(int64_t)row * lda + k] : 0.f;
-          rb[j][e] = (row < N && k < K) ? B[(int64_t)row * ldb + k] : 0.f;
-        }
-      }
-    }
-  };
-  auto sstore = [&](int st) {
-    float *As = lds + st * STAGE32;
-    float *Bs = As + GEMM_UNIT * S32;
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      *(fvec4 *)(As + (lrow + 64 * j) * S32 + lk) = ra[j];
-      *(fvec4 *)(Bs + (lrow + 64 * j) * S32 + lk) = rb[j];
-    }
-  };
-  const int nst = (K + KC32 - 1) / KC32;
-  gload(0);
-  sstore(0);
-  __syncthreads();
-  for (int st = 0; st < nst; ++st) {
-    const int cur = st & 1;
-    if (st + 1 < nst) gload((st + 1) * KC32);
-    const float *As = lds + cur * STAGE32;
-    const float *Bs = As + GEMM_UNIT * S32;
-#pragma unroll
-    for (int ks = 0; ks < KC32 / 4; ++ks) {
-      const int kk = 4 * ks + kq;
-      float a[4], b[2];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] = As[(64 * wr + 16 * i + l16) * S32 + kk];
-#pragma unroll
-      for (int c = 0; c < 2; ++c) b[c] = Bs[(32 * wc + 16 * c + l16) * S32 + kk];
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int c = 0; c < 2; ++c)
-          acc[i][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[c], acc[i][c], 0, 0, 0);
-    }
-    if (st + 1 < nst) sstore(cur ^ 1);
-    __syncthreads();
-  }
-  store_lowp<TOUT>(C, ldc, M, N, lower_only, acc);
 }
 
 constexpr int KC16 = 64;
@@ -416,58 +466,49 @@ __device__ __forceinline__ UnitBlock unit_block(const TaskDesc &d, int unit, int
   return u;
 }
 
-__device__ __forceinline__ void run_unit_f64(const TaskDesc &d, int unit, double *lds, int tid) {
-  const UnitBlock u = unit_block(d, unit, 8);
+template <int TA>
+__device__ __forceinline__ void run_unit_pair(const TaskDesc &d, int unit, double *lds, int tid) {
+  const UnitBlock u = unit_block(d, unit, TA == T_F64 ? 8 : 4);
   // buffer resources must sit in scalar registers: make the wave-uniform
   // unit fields provably uniform so no per-lane resource loop is generated
   auto su64 = [](const void *p) { return (void *)uniform_u64((uint64_t)p); };
   auto s32 = [](int64_t v) { return (int64_t)(int)__builtin_amdgcn_readfirstlane((int)v); };
-  void *C = su64((double *)d.c + u.coff);
+  void *C = su64((char *)d.c + u.coff * (d.tc == T_F64 ? 8 : 4));
   const void *a = su64(u.a), *b = su64(u.b);
   const int64_t ldc = s32(d.ldc), lda = s32(u.lda), ldb = s32(u.ldb);
   const int M = __builtin_amdgcn_readfirstlane(u.M), N = __builtin_amdgcn_readfirstlane(u.N);
   const int K = __builtin_amdgcn_readfirstlane(d.k);
   const int dlim = __builtin_amdgcn_readfirstlane(u.lower_only ? 0 : GEMM_UNIT);
-  if (M == GEMM_UNIT && N == GEMM_UNIT && K % KC64 == 0)
-    block_f64<true>(C, ldc, a, lda, b, ldb, M, N, K, dlim, lds, tid);
-  else
-    block_f64<false>(C, ldc, a, lda, b, ldb, M, N, K, dlim, lds, tid);
-}
-
-// One work item of the FP64 kernel: units u0 and u0 + 1 of one task, one per
-// half.  Both have the task's K and so pass the same number of workgroup
-// barriers; a half without a unit (odd unit count) only passes them.
-__device__ __forceinline__ void run_pair_f64(const TaskDesc &d, int u0, double *lds) {
-  const int half = threadIdx.x >> 8, tid = threadIdx.x & 255;
-  const int unit = u0 + half;
-  if (unit < __builtin_amdgcn_readfirstlane(d.nunits)) {
-    run_unit_f64(d, unit, lds + half * 2 * STAGE64, tid);
+  const bool full = M == GEMM_UNIT && N == GEMM_UNIT;
+  if constexpr (TA == T_F64) {
+    if (full && K % KC64 == 0)
+      block_f64<true>(C, ldc, a, lda, b, ldb, M, N, K, dlim, lds, tid);
+    else
+      block_f64<false>(C, ldc, a, lda, b, ldb, M, N, K, dlim, lds, tid);
   } else {
-    const int nst = (__builtin_amdgcn_readfirstlane(d.k) + KC64 - 1) / KC64;
-    for (int i = 0; i <= nst; ++i) __syncthreads();
+    // FP32 inputs: two-float loads need 8-byte aligned rows
+    const bool f2 = full && K % KCF == 0 && ((lda | ldb) & 1) == 0 &&
+                    (((uintptr_t)a | (uintptr_t)b) & 7) == 0;
+    float *fl = (float *)lds;
+    if (__builtin_amdgcn_readfirstlane(d.tc) == T_F64) {
+      if (f2) block_f32p<true, double>(C, ldc, a, lda, b, ldb, M, N, K, dlim, fl, tid);
+      else block_f32p<false, double>(C, ldc, a, lda, b, ldb, M, N, K, dlim, fl, tid);
+    } else {
+      if (f2) block_f32p<true, float>(C, ldc, a, lda, b, ldb, M, N, K, dlim, fl, tid);
+      else block_f32p<false, float>(C, ldc, a, lda, b, ldb, M, N, K, dlim, fl, tid);
+    }
   }
 }
 
 __device__ __forceinline__ void run_unit_lowp(const TaskDesc &d, int unit, double *lds) {
-  if (d.ta == T_F32) {
-    const UnitBlock u = unit_block(d, unit, 4);
-    const gfloat *A = (const gfloat *)u.a, *B = (const gfloat *)u.b;
-    if (d.tc == T_F64)
-      block_f32<double>((gdouble *)d.c + u.coff, d.ldc, A, u.lda, B, u.ldb, u.M, u.N, d.k,
-                         u.lower_only, (float *)lds);
-    else
-      block_f32<float>((gfloat *)d.c + u.coff, d.ldc, A, u.lda, B, u.ldb, u.M, u.N, d.k,
-                        u.lower_only, (float *)lds);
-  } else {
-    const UnitBlock u = unit_block(d, unit, 2);
-    const gbf16 *A = (const gbf16 *)u.a, *B = (const gbf16 *)u.b;
-    if (d.tc == T_F64)
-      block_bf16<double>((gdouble *)d.c + u.coff, d.ldc, A, u.lda, B, u.ldb, u.M, u.N, d.k,
-                          u.lower_only, (__bf16 *)lds);
-    else
-      block_bf16<float>((gfloat *)d.c + u.coff, d.ldc, A, u.lda, B, u.ldb, u.M, u.N, d.k,
-                         u.lower_only, (__bf16 *)lds);
-  }
+  const UnitBlock u = unit_block(d, unit, 2);
+  const gbf16 *A = (const gbf16 *)u.a, *B = (const gbf16 *)u.b;
+  if (d.tc == T_F64)
+    block_bf16<double>((gdouble *)d.c + u.coff, d.ldc, A, u.lda, B, u.ldb, u.M, u.N, d.k,
+                        u.lower_only, (__bf16 *)lds);
+  else
+    block_bf16<float>((gfloat *)d.c + u.coff, d.ldc, A, u.lda, B, u.ldb, u.M, u.N, d.k,
+                       u.lower_only, (__bf16 *)lds);
 }
 
 // Persistent loop of a GEMM kernel: take units from the level's counter
@@ -504,28 +545,48 @@ __device__ __forceinline__ void unit_loop(const LevelArgs &A, double *lds, RUN r
   }
 }
 
-// FP64 GEMM/SYRK units (two workgroups per CU).
+// One work item of the two-half kernel: units u0 and u0 + 1 of one task, one
+// per half.  Both have the task's K and so pass the same number of
+// workgroup barriers; a half without a unit (odd unit count) only passes
+// them.  One kernel instance per input type (FP64 or FP32), so each keeps
+// its own register allocation.
+template <int TA>
+__device__ __forceinline__ void run_pair(const TaskDesc &d, int u0, double *lds) {
+  const int half = threadIdx.x >> 8, tid = threadIdx.x & 255;
+  const int unit = u0 + half;
+  if (unit < __builtin_amdgcn_readfirstlane(d.nunits)) {
+    run_unit_pair<TA>(d, unit, lds + half * 2 * STAGE64, tid);
+  } else {
+    constexpr int kc = TA == T_F64 ? KC64 : KCF;
+    const int nst = (__builtin_amdgcn_readfirstlane(d.k) + kc - 1) / kc;
+    for (int i = 0; i <= nst; ++i) __syncthreads();
+  }
+}
+template <int TA>
 __global__ void __launch_bounds__(GT64, 1) dc_gemm_kernel(LevelArgs A) {
   extern __shared__ double lds[];
-  unit_loop(A, lds, [](const TaskDesc &d, int u, double *l) { run_pair_f64(d, u, l); });
+  unit_loop(A, lds, [](const TaskDesc &d, int u, double *l) { run_pair<TA>(d, u, l); });
 }
 
-// GEMM/SYRK units with FP32 or BF16 inputs.
+// GEMM/SYRK units with BF16 inputs.
 __global__ void __launch_bounds__(GT, 1) dc_gemm_lowp_kernel(LevelArgs A) {
   extern __shared__ double lds[];
   unit_loop(A, lds, [](const TaskDesc &d, int u, double *l) { run_unit_lowp(d, u, l); });
 }
 
 constexpr int GEMM_KERNEL_LDS = 2 * 2 * STAGE64 * (int)sizeof(double);   // two halves
-constexpr int GEMM_LOWP_LDS = 2 * STAGE32 * (int)sizeof(float);
-static_assert(2 * STAGE16 * 2 <= GEMM_LOWP_LDS, "bf16 lds");
+constexpr int GEMM_LOWP_LDS = 2 * STAGE16 * 2;   // two stages of BF16 A and B
 static_assert(GEMM_KERNEL_LDS + 64 <= 160 * 1024, "FP64 workgroup LDS");
 
 }  // namespace
 
-int dcx_launch_gemm(const LevelArgs &args, int workers, void *stream) {
-  hipLaunchKernelGGL(dc_gemm_kernel, dim3(workers), dim3(GT64), GEMM_KERNEL_LDS,
-                     (hipStream_t)stream, args);
+int dcx_launch_gemm(const LevelArgs &args, int workers, int ta, void *stream) {
+  if (ta == T_F64)
+    hipLaunchKernelGGL(dc_gemm_kernel<T_F64>, dim3(workers), dim3(GT64), GEMM_KERNEL_LDS,
+                       (hipStream_t)stream, args);
+  else
+    hipLaunchKernelGGL(dc_gemm_kernel<T_F32>, dim3(workers), dim3(GT64), GEMM_KERNEL_LDS,
+                       (hipStream_t)stream, args);
   return (int)hipGetLastError();
 }
 
@@ -536,8 +597,11 @@ int dcx_launch_gemm_lowp(const LevelArgs &args, int workers, void *stream) {
 }
 
 int dcx_gemm_setup(void) {
-  hipError_t e = hipFuncSetAttribute((const void *)dc_gemm_kernel,
+  hipError_t e = hipFuncSetAttribute((const void *)dc_gemm_kernel<T_F64>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, GEMM_KERNEL_LDS);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void *)dc_gemm_kernel<T_F32>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, GEMM_KERNEL_LDS);
   if (e == hipSuccess)
     e = hipFuncSetAttribute((const void *)dc_gemm_lowp_kernel,
                             hipFuncAttributeMaxDynamicSharedMemorySize, GEMM_LOWP_LDS);

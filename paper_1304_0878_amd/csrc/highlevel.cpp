@@ -101,19 +101,46 @@ int dcx_submit_potrf_tiles(dc_runtime *rt, const std::vector<dc_handle> &A, int6
 }
 
 // Forward then backward sweep on partitioned L tiles and RHS row blocks.
+// With V (the inverses of the diagonal factors; 0 where there is none) the
+// diagonal steps are products with them (TRSM_L_INV, TRSM_LT_INV).
 int dcx_submit_potrs_tiles(dc_runtime *rt, const std::vector<dc_handle> &L, int64_t T,
-                           const std::vector<dc_handle> &B) {
+                           const std::vector<dc_handle> &B, const std::vector<dc_handle> *V) {
   auto at = [&](int64_t i, int64_t j) { return L[i * T + j]; };
+  auto inv = [&](int64_t k) { return V && (*V)[k] != 0; };
   for (int64_t k = 0; k < T; ++k) {
-    TRY(submit2(rt, DC_TRSM_L, at(k, k), DC_R, B[k], DC_RW, 0));
+    if (inv(k))
+      TRY(submit3(rt, DC_TRSM_L_INV, at(k, k), DC_R, (*V)[k], DC_R, B[k], DC_RW, 0));
+    else
+      TRY(submit2(rt, DC_TRSM_L, at(k, k), DC_R, B[k], DC_RW, 0));
     for (int64_t i = k + 1; i < T; ++i)
       TRY(submit3(rt, DC_GEMM_RHS_N, at(i, k), DC_R, B[k], DC_R, B[i], DC_RW, i == k + 1 ? 0 : 1));
   }
   for (int64_t k = T - 1; k >= 0; --k) {
-    TRY(submit2(rt, DC_TRSM_LT, at(k, k), DC_R, B[k], DC_RW, 0));
+    if (inv(k))
+      TRY(submit3(rt, DC_TRSM_LT_INV, at(k, k), DC_R, (*V)[k], DC_R, B[k], DC_RW, 0));
+    else
+      TRY(submit2(rt, DC_TRSM_LT, at(k, k), DC_R, B[k], DC_RW, 0));
     for (int64_t i = k - 1; i >= 0; --i)
       TRY(submit3(rt, DC_GEMM_RHS_T, at(k, i), DC_R, B[k], DC_R, B[i], DC_RW, i == k - 1 ? 0 : 1));
   }
+  return 0;
+}
+
+// Grows the runtime's inverse workspace to at least `bytes`; the previous
+// contents are not kept.
+static int inv_workspace(dc_runtime *rt, int64_t bytes) {
+  if (rt->inv_ws_bytes >= bytes) return 0;
+  if (rt->inv_ws) {
+    if (hipStreamSynchronize(rt->stream) != hipSuccess) return -EIO;
+    hipFree(rt->inv_ws);
+    rt->inv_ws = nullptr;
+    rt->inv_ws_bytes = 0;
+  }
+  if (hipMalloc(&rt->inv_ws, bytes) != hipSuccess) {
+    rt->inv_ws = nullptr;
+    return -ENOMEM;
+  }
+  rt->inv_ws_bytes = bytes;
   return 0;
 }
 
@@ -132,20 +159,7 @@ extern "C" int dc_potrf(dc_runtime *rt, dc_handle A, int64_t tile) {
   dc_handle wh = 0;
   Tiles tw;
   if (inv) {
-    const int64_t bytes = (T - 1) * tile * tile * 8;
-    if (rt->inv_ws_bytes < bytes) {
-      if (rt->inv_ws) {
-        if (hipStreamSynchronize(rt->stream) != hipSuccess) return -EIO;
-        hipFree(rt->inv_ws);
-        rt->inv_ws = nullptr;
-        rt->inv_ws_bytes = 0;
-      }
-      if (hipMalloc(&rt->inv_ws, bytes) != hipSuccess) {
-        rt->inv_ws = nullptr;
-        return -ENOMEM;
-      }
-      rt->inv_ws_bytes = bytes;
-    }
+    TRY(inv_workspace(rt, (T - 1) * tile * tile * 8));
     TRY(dc_matrix_register(rt, &wh, rt->inv_ws, (T - 1) * tile, tile, tile, DC_F64));
     const int e = tw.open(rt, wh, tile);
     if (e) { dc_unregister(rt, wh); return e; }
@@ -178,17 +192,49 @@ extern "C" int dc_potrs(dc_runtime *rt, dc_handle L, dc_handle B, int64_t tile) 
     return -EINVAL;
   if (pl->partitioned || pb->partitioned) return -EBUSY;
   if (pl->rows == 0 || pb->cols == 0) return 0;
-  Tiles tl, tb;
-  TRY(tl.open(rt, L, tile));
-  TRY(tb.open(rt, B, tile));
-  // each column block of B is an independent right-hand-side group
-  std::vector<dc_handle> rows(tl.tr);
-  for (int64_t j = 0; j < tb.tc; ++j) {
-    for (int64_t i = 0; i < tl.tr; ++i) rows[i] = tb.at(i, j);
-    int e = dcx_submit_potrs_tiles(rt, tl.ids, tl.tr, rows);
-    if (e) { dcx_discard_pending(rt); return e; }
+  const int64_t n = pl->rows;
+  const int64_t T = (n + tile - 1) / tile;
+  const int64_t last = n - (T - 1) * tile;
+  // inverses of the diagonal factors (tiles of order >= 16): TRTRI for all
+  // of them first, in parallel, then products in place of the diagonal
+  // substitutions of both sweeps
+  const bool inv = tile >= 16 && rt->cfg.device >= 0;
+  dc_handle hw = 0, hl = 0;
+  Tiles tw;
+  std::vector<dc_handle> V;
+  int e = 0;
+  if (inv) {
+    TRY(inv_workspace(rt, T * tile * tile * 8));
+    V.assign(T, 0);
+    if (T > 1) {
+      TRY(dc_matrix_register(rt, &hw, rt->inv_ws, (T - 1) * tile, tile, tile, DC_F64));
+      e = tw.open(rt, hw, tile);
+      for (int64_t k = 0; k + 1 < T && !e; ++k) V[k] = tw.at(k, 0);
+    }
+    if (!e && last >= 16)
+      e = dc_matrix_register(rt, &hl, (char *)rt->inv_ws + (T - 1) * tile * tile * 8, last, last,
+                             tile, DC_F64);
+    if (!e && hl) V[T - 1] = hl;
   }
-  return dc_wait_all(rt);
+  if (!e) {
+    Tiles tl, tb;
+    e = tl.open(rt, L, tile);
+    if (!e) e = tb.open(rt, B, tile);
+    for (int64_t k = 0; k < T && inv && !e; ++k)
+      if (V[k]) e = submit2(rt, DC_TRTRI, tl.at(k, k), DC_R, V[k], DC_W, 0);
+    // each column block of B is an independent right-hand-side group
+    std::vector<dc_handle> rows(tl.tr);
+    for (int64_t j = 0; j < tb.tc && !e; ++j) {
+      for (int64_t i = 0; i < tl.tr; ++i) rows[i] = tb.at(i, j);
+      e = dcx_submit_potrs_tiles(rt, tl.ids, tl.tr, rows, inv ? &V : nullptr);
+    }
+    if (e) dcx_discard_pending(rt);
+    else e = dc_wait_all(rt);
+  }
+  tw.close();
+  if (hw) { const int e2 = dc_unregister(rt, hw); if (!e) e = e2; }
+  if (hl) { const int e2 = dc_unregister(rt, hl); if (!e) e = e2; }
+  return e;
 }
 
 // Many independent factorisations (and solves) in one graph: one flush, one
@@ -226,7 +272,7 @@ extern "C" int dc_potrf_batched(dc_runtime *rt, int64_t count, const dc_handle *
       std::vector<dc_handle> rows(ta[i].tr);
       for (int64_t j = 0; j < tb[i].tc && !err; ++j) {
         for (int64_t r = 0; r < ta[i].tr; ++r) rows[r] = tb[i].at(r, j);
-        err = dcx_submit_potrs_tiles(rt, ta[i].ids, ta[i].tr, rows);
+        err = dcx_submit_potrs_tiles(rt, ta[i].ids, ta[i].tr, rows, nullptr);
       }
     }
   }

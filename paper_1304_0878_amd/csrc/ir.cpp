@@ -21,7 +21,7 @@
 int dcx_submit_potrf_tiles(dc_runtime *rt, const std::vector<dc_handle> &A, int64_t T,
                            const std::vector<dc_handle> *W);
 int dcx_submit_potrs_tiles(dc_runtime *rt, const std::vector<dc_handle> &L, int64_t T,
-                           const std::vector<dc_handle> &B);
+                           const std::vector<dc_handle> &B, const std::vector<dc_handle> *V);
 
 namespace {
 
@@ -90,9 +90,12 @@ double now_ms() {
 // Submits the factorisation of A (FP64 lower, partitioned tiles At) at update
 // precision upd into the workspace: D[k] FP64 diagonal tiles, W (FP32) and S
 // (BF16) off-diagonal tile handles.  For upd == FP64 the tiles W are FP64.
+// With V (T - 1 FP64 tiles), the panel solves of column k are TRTRI(D[k])
+// into V[k] and TRSM_INV (TRSM_INV_CAST for BF16) instead of TRSM.
 int submit_mixed_factor(dc_runtime *rt, int64_t T, int64_t tile, const std::vector<dc_handle> &At,
                         const std::vector<dc_handle> &D, const std::vector<dc_handle> &W,
-                        const std::vector<dc_handle> &S, dc_dtype upd) {
+                        const std::vector<dc_handle> &S, dc_dtype upd,
+                        const std::vector<dc_handle> *V) {
   auto a = [&](int64_t i, int64_t j) { return At[i * T + j]; };
   auto w = [&](int64_t i, int64_t j) { return W[i * T + j]; };
   auto s = [&](int64_t i, int64_t j) { return S[i * T + j]; };
@@ -105,9 +108,16 @@ int submit_mixed_factor(dc_runtime *rt, int64_t T, int64_t tile, const std::vect
   for (int64_t k = 0; k < T; ++k) {
     const int64_t row0 = k * tile;
     TRY(submit(rt, DC_POTRF, {D[k]}, {DC_RW}, 0, &row0, sizeof(row0)));
+    const bool inv = V && k + 1 < T;
+    if (inv) TRY(submit(rt, DC_TRTRI, {D[k], (*V)[k]}, {DC_R, DC_W}, 0));
     for (int64_t i = k + 1; i < T; ++i) {
       const int pr = i == k + 1 ? 0 : 1;
-      if (bf)
+      if (inv && bf)
+        TRY(submit(rt, DC_TRSM_INV_CAST, {D[k], (*V)[k], w(i, k), s(i, k)},
+                   {DC_R, DC_R, DC_RW, DC_W}, pr));
+      else if (inv)
+        TRY(submit(rt, DC_TRSM_INV, {D[k], (*V)[k], w(i, k)}, {DC_R, DC_R, DC_RW}, pr));
+      else if (bf)
         TRY(submit(rt, DC_TRSM_CAST, {D[k], w(i, k), s(i, k)}, {DC_R, DC_RW, DC_W}, pr));
       else
         TRY(submit(rt, DC_TRSM, {D[k], w(i, k)}, {DC_R, DC_RW}, pr));
@@ -163,7 +173,12 @@ extern "C" int dc_posv_ir(dc_runtime *rt, dc_handle A, dc_handle B, dc_handle X,
     const size_t o_w = al(o_d + (size_t)T * tile * tile * 8);
     const size_t o_s = al(o_w + (size_t)n * n * es);
     const size_t o_r = al(o_s + (prec == DC_BF16 ? (size_t)n * n * 2 : 0));
-    const size_t total = al(o_r + (size_t)n * r * 8);
+    // inverses of the diagonal factors: panel solves and the diagonal steps
+    // of every solve become MFMA products
+    const bool inv = tile >= 16;
+    const int64_t nlast = n - (T - 1) * tile;
+    const size_t o_v = al(o_r + (size_t)n * r * 8);
+    const size_t total = al(o_v + (inv ? (size_t)T * tile * tile * 8 : 0));
     TRY(ws.get(total));
     char *base = (char *)ws.ptr;
     Regs regs(rt);
@@ -171,6 +186,11 @@ extern "C" int dc_posv_ir(dc_runtime *rt, dc_handle A, dc_handle B, dc_handle X,
     TRY(regs.mat(&hW, base + o_w, n, n, n, prec == DC_F64 ? DC_F64 : DC_F32, A));
     if (prec == DC_BF16) TRY(regs.mat(&hS, base + o_s, n, n, n, DC_BF16, A));
     TRY(regs.mat(&hR, base + o_r, n, r, r, DC_F64, 0));
+    dc_handle hV = 0, hVl = 0;   // tiles 0..T-2, and the last (if of order >= 16)
+    if (inv && T > 1) TRY(regs.mat(&hV, base + o_v, (T - 1) * tile, tile, tile, DC_F64, A));
+    if (inv && nlast >= 16)
+      TRY(regs.mat(&hVl, base + o_v + (size_t)(T - 1) * tile * tile * 8, nlast, nlast, tile,
+                   DC_F64, A));
     std::vector<dc_handle> D(T);
     for (int64_t k = 0; k < T; ++k) {
       const int64_t nb = std::min(tile, n - k * tile);
@@ -181,12 +201,15 @@ extern "C" int dc_posv_ir(dc_runtime *rt, dc_handle A, dc_handle B, dc_handle X,
     double t0 = now_ms();
     int64_t info = 0;
     {
-      std::vector<dc_handle> At(T * T), W(T * T), S(T * T, 0);
+      std::vector<dc_handle> At(T * T), W(T * T), S(T * T, 0), V(inv ? T - 1 : 0);
       TRY(dc_matrix_partition(rt, A, tile, At.data()));
       int e = dc_matrix_partition(rt, hW, tile, W.data());
       if (!e && hS) e = dc_matrix_partition(rt, hS, tile, S.data());
-      if (!e) e = submit_mixed_factor(rt, T, tile, At, D, W, S, prec);
+      if (!e && hV) e = dc_matrix_partition(rt, hV, tile, V.data());
+      if (!e) e = submit_mixed_factor(rt, T, tile, At, D, W, S, prec, hV ? &V : nullptr);
+      if (!e && hVl) e = submit(rt, DC_TRTRI, {D[T - 1], hVl}, {DC_R, DC_W}, 0);
       if (!e) e = dc_wait_all(rt);
+      if (hV) dc_matrix_unpartition(rt, hV);
       if (hS) dc_matrix_unpartition(rt, hS);
       dc_matrix_unpartition(rt, hW);
       dc_matrix_unpartition(rt, A);
@@ -203,8 +226,13 @@ extern "C" int dc_posv_ir(dc_runtime *rt, dc_handle A, dc_handle B, dc_handle X,
 
     // ---- solve and refine
     double t1 = now_ms();
-    std::vector<dc_handle> Wt(T * T), L(T * T), Xb, Rb;
+    std::vector<dc_handle> Wt(T * T), L(T * T), Xb, Rb, Vall;
     TRY(dc_matrix_partition(rt, hW, tile, Wt.data()));
+    if (inv) {
+      Vall.assign(T, 0);
+      if (hV) TRY(dc_matrix_partition(rt, hV, tile, Vall.data()));
+      Vall[T - 1] = hVl;
+    }
     for (int64_t i = 0; i < T; ++i)
       for (int64_t j = 0; j < T; ++j) L[i * T + j] = i == j ? D[i] : Wt[i * T + j];
     auto solve_into = [&](dc_handle V) -> int {
@@ -216,7 +244,7 @@ extern "C" int dc_posv_ir(dc_runtime *rt, dc_handle A, dc_handle B, dc_handle X,
       int e = 0;
       for (int64_t j = 0; j < tc && !e; ++j) {
         for (int64_t i = 0; i < T; ++i) rows[i] = vt[i * tc + j];
-        e = dcx_submit_potrs_tiles(rt, L, T, rows);
+        e = dcx_submit_potrs_tiles(rt, L, T, rows, inv ? &Vall : nullptr);
       }
       if (!e) e = dc_wait_all(rt);
       dc_matrix_unpartition(rt, V);
@@ -272,6 +300,7 @@ extern "C" int dc_posv_ir(dc_runtime *rt, dc_handle A, dc_handle B, dc_handle X,
       if (++it >= maxit) break;
       prev = dn;
     }
+    if (inv && hV) dc_matrix_unpartition(rt, hV);
     dc_matrix_unpartition(rt, hW);
     TRY(e);
     rep->refine_ms = now_ms() - t1;

@@ -354,6 +354,9 @@ static const KindSig kSig[DC_NUM_KINDS] = {
     {3, {DC_R, DC_RW, DC_W}},           // TRSM_CAST
     {2, {DC_R, DC_W}},                  // TRTRI
     {3, {DC_R, DC_R, DC_RW}},           // TRSM_INV
+    {4, {DC_R, DC_R, DC_RW, DC_W}},     // TRSM_INV_CAST
+    {3, {DC_R, DC_R, DC_RW}},           // TRSM_L_INV
+    {3, {DC_R, DC_R, DC_RW}},           // TRSM_LT_INV
 };
 
 static int units_for(const TaskDesc &d) {
@@ -361,9 +364,10 @@ static int units_for(const TaskDesc &d) {
   switch (d.kind) {
     case K_GEMM: return std::max(1, cdiv(d.m, GEMM_UNIT) * cdiv(d.n, GEMM_UNIT));
     case K_SYRK: { int p = cdiv(d.m, GEMM_UNIT); return std::max(1, p * (p + 1) / 2); }
-    case K_TRSM: case K_TRSM_CAST: case K_TRTRI: case K_TRSM_INV:
+    case K_TRSM: case K_TRSM_CAST: case K_TRTRI: case K_TRSM_INV: case K_TRSM_INV_CAST:
       return std::max(1, cdiv(d.m, trsm_rows(d.n)));
     case K_GEMM_RHS_N: case K_GEMM_RHS_T: return std::max(1, cdiv(d.m, RHS_ROWS));
+    case K_TRSM_L_INV: case K_TRSM_LT_INV: return std::max(1, cdiv(d.n, 16));
     case K_CAST: case K_RESID: case K_AXPY:
       return std::max(1, cdiv(d.m, ROW_UNIT));
     case K_SCAL: return std::max(1, cdiv(d.m, 4096));
@@ -418,7 +422,7 @@ static int make_desc(dc_runtime *rt, dc_kind kind, const std::vector<Handle *> &
       d.c = W->ptr; d.ldc = W->ld; d.tc = W->dtype;
       break;
     }
-    case DC_TRSM_INV: {
+    case DC_TRSM_INV: case DC_TRSM_INV_CAST: {
       Handle *L = H[0], *W = H[1], *X = H[2];
       if (!f64(L) || !f64(W) || (X->dtype != DC_F64 && X->dtype != DC_F32)) return -EINVAL;
       if (L->rows != L->cols || W->rows != L->rows || W->cols != L->rows ||
@@ -428,6 +432,12 @@ static int make_desc(dc_runtime *rt, dc_kind kind, const std::vector<Handle *> &
       d.a = W->ptr; d.lda = W->ld; d.ta = W->dtype;
       d.b = L->ptr; d.ldb = L->ld; d.tb = L->dtype;
       d.c = X->ptr; d.ldc = X->ld; d.tc = X->dtype;
+      if (kind == DC_TRSM_INV_CAST) {
+        Handle *S = H[3];
+        if (X->dtype != DC_F32 || S->dtype != DC_BF16 || S->rows != X->rows || S->cols != X->cols)
+          return -EINVAL;
+        d.d = S->ptr; d.ldd = S->ld;
+      }
       break;
     }
     case DC_SYRK: {
@@ -457,6 +467,18 @@ static int make_desc(dc_runtime *rt, dc_kind kind, const std::vector<Handle *> &
       if (L->rows != L->cols || B->rows != L->rows) return -EINVAL;
       d.m = (int)L->rows; d.n = (int)B->cols;
       d.a = L->ptr; d.lda = L->ld; d.ta = L->dtype;
+      d.c = B->ptr; d.ldc = B->ld; d.tc = B->dtype;
+      break;
+    }
+    case DC_TRSM_L_INV: case DC_TRSM_LT_INV: {
+      Handle *L = H[0], *W = H[1], *B = H[2];
+      if (!f64(L) || !f64(W) || !f64(B)) return -EINVAL;
+      if (L->rows != L->cols || W->rows != L->rows || W->cols != L->rows ||
+          B->rows != L->rows || L->rows < 16 || L->rows > MAX_TILE)
+        return -EINVAL;
+      d.m = (int)L->rows; d.n = (int)B->cols;
+      d.a = W->ptr; d.lda = W->ld; d.ta = W->dtype;
+      d.b = L->ptr; d.ldb = L->ld; d.tb = L->dtype;
       d.c = B->ptr; d.ldc = B->ld; d.tc = B->dtype;
       break;
     }
@@ -545,7 +567,8 @@ extern "C" int dc_task_submit(dc_runtime *rt, dc_kind kind, int nbuf, const dc_h
   if (rt->tasks.size() >= (size_t)INT32_MAX / 2) return -ENOMEM;
 
   // numerical-status slot: the root matrix of the factor this task touches
-  if (kind <= DC_GEMM_RHS_T || kind == DC_TRSM_CAST || kind == DC_TRTRI || kind == DC_TRSM_INV) {
+  if (kind <= DC_GEMM_RHS_T || kind == DC_TRSM_CAST || kind == DC_TRTRI || kind == DC_TRSM_INV ||
+      kind == DC_TRSM_INV_CAST || kind == DC_TRSM_L_INV || kind == DC_TRSM_LT_INV) {
     const dc_handle root = rt->status_root_of(bufs[0]);
     auto it = rt->slot_of.find(root);
     int slot;
@@ -701,12 +724,13 @@ static void task_work(const TaskDesc &d, double *flops, double *bytes) {
     case K_TRSM_CAST: *flops = m * n * n; *bytes = 8 * tri_n + 2 * 4 * m * n + 2 * m * n; break;
     case K_TRTRI: *flops = n * n * n / 3; *bytes = 2 * 8 * tri_n; break;
     case K_TRSM_INV: *flops = m * n * n; *bytes = 8 * tri_n + 2 * esize(d.tc) * m * n; break;
+    case K_TRSM_INV_CAST: *flops = m * n * n; *bytes = 8 * tri_n + 2 * 4 * m * n + 2 * m * n; break;
     case K_SYRK: *flops = m * (m + 1) * k; *bytes = esize(d.ta) * m * k + 2 * esize(d.tc) * tri_m; break;
     case K_GEMM:
       *flops = 2 * m * n * k;
       *bytes = esize(d.ta) * m * k + esize(d.tb) * n * k + 2 * esize(d.tc) * m * n;
       break;
-    case K_TRSM_L: case K_TRSM_LT:
+    case K_TRSM_L: case K_TRSM_LT: case K_TRSM_L_INV: case K_TRSM_LT_INV:
       *flops = m * m * n; *bytes = esize(d.ta) * tri_m + 2 * 8 * m * n; break;
     case K_GEMM_RHS_N: case K_GEMM_RHS_T:
       *flops = 2 * m * n * k; *bytes = esize(d.ta) * m * k + 8 * k * n + 2 * 8 * m * n; break;
@@ -721,10 +745,12 @@ static void task_work(const TaskDesc &d, double *flops, double *bytes) {
 // LDS bytes the level kernel needs for a unit of this task.
 static size_t lds_for(const TaskDesc &d) {
   switch (d.kind) {
-    case K_TRSM: case K_TRSM_CAST: case K_TRTRI: case K_TRSM_INV:
+    case K_TRSM: case K_TRSM_CAST: case K_TRTRI: case K_TRSM_INV: case K_TRSM_INV_CAST:
       return (size_t)trsm_lds_doubles(d.n) * 8;
     case K_POTRF: return (size_t)potrf_lds_doubles(d.m) * 8;
     case K_TRSM_L: case K_TRSM_LT: return (size_t)solve_lds_doubles(d.m) * 8;
+    case K_TRSM_L_INV: case K_TRSM_LT_INV:
+      return (size_t)std::max(solve_lds_doubles(d.m), TRSM_ROWS * panel_stride(d.m)) * 8;
     case K_GEMM_RHS_N: case K_GEMM_RHS_T: return (size_t)RHS_LDS_DOUBLES * 8;
     case K_RESID: return (size_t)(2 * 64 * 8 + 4 * 64 * 8) * 8;
     default: return 16;
@@ -739,9 +765,10 @@ static double cost_ns(const TaskDesc &d) {
     case K_SYRK: return m * m * k / (d.ta == T_F64 ? 200.0 : 400.0);
     case K_TRSM: case K_TRSM_CAST: return m * n * n / 20.0;
     case K_TRTRI: return n * n * n / 28.0;
-    case K_TRSM_INV: return m * n * n / 50.0;
+    case K_TRSM_INV: case K_TRSM_INV_CAST: return m * n * n / 50.0;
     case K_POTRF: return m * m * m / 3.0 / 30.0 + 2000.0;
     case K_TRSM_L: case K_TRSM_LT: return m * m * 8.0 / 20.0 + 2000.0;
+    case K_TRSM_L_INV: case K_TRSM_LT_INV: return m * m * 8.0 / 100.0 + 2000.0;
     case K_GEMM_RHS_N: case K_GEMM_RHS_T: return m * k * 8.0 / 50.0;
     case K_RESID: return m * m * 8.0 / 50.0;
     default: return 1000.0 + m * (n > 0 ? n : 1) * 8.0 / 50.0;
@@ -831,10 +858,11 @@ extern "C" int dc_flush(dc_runtime *rt) {
   // per level: panel-kernel units first, then GEMM/SYRK units
   auto is_gemm = [](const TaskDesc &d) { return d.kind == K_GEMM || d.kind == K_SYRK; };
   int64_t total_units = 0;
-  // GEMM/SYRK units of a level: FP64 ones first (their own kernel), then
-  // those with FP32/BF16 inputs
-  auto is_g64 = [](const TaskDesc &d) { return d.ta == T_F64; };
-  std::vector<int64_t> pcount(nl, 0), gcount(nl, 0), lcount(nl, 0), g64count(nl, 0);
+  // GEMM/SYRK units of a level: those with FP64 or FP32 inputs first (the
+  // two-half kernel), then those with BF16 inputs
+  auto is_g64 = [](const TaskDesc &d) { return d.ta == T_F64 || d.ta == T_F32; };
+  std::vector<int64_t> pcount(nl, 0), gcount(nl, 0), lcount(nl, 0), g64count(nl, 0),
+      g32count(nl, 0);
   std::vector<double> pcost(nl, 0.0), gcost(nl, 0.0);
   const bool timing = rt->ktiming;
   std::vector<double> wflops(timing ? 2 * nl : 0, 0.0), wbytes(timing ? 2 * nl : 0, 0.0);
@@ -851,7 +879,7 @@ extern "C" int dc_flush(dc_runtime *rt) {
     total_units += d.nunits;
     total_items += ni;
     (is_gemm(d) ? gcount : pcount)[level[t]] += ni;
-    if (paired(d)) g64count[level[t]] += ni;
+    if (paired(d)) (d.ta == T_F64 ? g64count : g32count)[level[t]] += ni;
     (is_gemm(d) ? gcost : pcost)[level[t]] += cost_ns(d);
     lcount[level[t]] += ni;
     if (timing) {
@@ -869,7 +897,7 @@ extern "C" int dc_flush(dc_runtime *rt) {
   auto take = [&](int64_t bytes) { int64_t o = off; off = align_up(off + bytes, 256); return o; };
   const int64_t o_desc = take(nt * (int64_t)sizeof(TaskDesc));
   const int64_t o_items = take(total_items * 8);
-  const int64_t o_cnt = take(3 * nl * 8);
+  const int64_t o_cnt = take(4 * nl * 8);
   const int64_t o_tail = off;
   const int64_t o_info = take(std::max(nslots_roots, 1) * 8);
   const int64_t o_failed = take(std::max(nslots_roots, 1) * 4);
@@ -907,8 +935,12 @@ extern "C" int dc_flush(dc_runtime *rt) {
     const double cy = cost_ns(rt->tasks[y].desc) / rt->tasks[y].desc.nunits;
     return cx > cy;
   });
-  std::vector<int64_t> fillp(lbegin), fillg(gbegin), filll(nl);
-  for (int64_t L = 0; L < nl; ++L) filll[L] = gbegin[L] + g64count[L];
+  // GEMM section of a level: FP64-input pairs, FP32-input pairs, BF16 units
+  std::vector<int64_t> fillp(lbegin), fillg(gbegin), fill32(nl), filll(nl);
+  for (int64_t L = 0; L < nl; ++L) {
+    fill32[L] = gbegin[L] + g64count[L];
+    filll[L] = fill32[L] + g32count[L];
+  }
   std::vector<size_t> llds(nl, 16);
   for (int64_t i = 0; i < nt; ++i) {
     const int64_t t = order[i];
@@ -917,12 +949,14 @@ extern "C" int dc_flush(dc_runtime *rt) {
     const int L = level[t];
     const bool g = is_gemm(k.desc);
     if (!g) llds[L] = std::max(llds[L], lds_for(k.desc));
-    int64_t &fp = !g ? fillp[L] : is_g64(k.desc) ? fillg[L] : filll[L];
+    int64_t &fp = !g ? fillp[L]
+                  : !is_g64(k.desc) ? filll[L]
+                  : k.desc.ta == T_F64 ? fillg[L] : fill32[L];
     const int step = paired(k.desc) ? 2 : 1;
     for (int u = 0; u < k.desc.nunits; u += step)
       items[fp++] = ((uint64_t)(uint32_t)t << 32) | (uint32_t)u;
   }
-  memset(hb + o_cnt, 0, 3 * nl * 8);
+  memset(hb + o_cnt, 0, 4 * nl * 8);
   memset(hb + o_info, 0, std::max(nslots_roots, 1) * 8);
   memset(hb + o_failed, 0, std::max(nslots_roots, 1) * 4);
   if (trace) {
@@ -991,7 +1025,7 @@ extern "C" int dc_flush(dc_runtime *rt) {
     if (hasp) {
       a.begin = lbegin[L];
       a.count = pcount[L];
-      a.counter = (unsigned long long *)(db + o_cnt) + 3 * L;
+      a.counter = (unsigned long long *)(db + o_cnt) + 4 * L;
       const size_t tb = timing ? tev(pstream) : 0;
       int le = dcx_launch_level(a, pworkers, llds[L], pstream);
       if (le != 0) { fail_hip((hipError_t)le, "level launch"); drop(); return -EIO; }
@@ -1003,24 +1037,21 @@ extern "C" int dc_flush(dc_runtime *rt) {
     }
     if (hasg) {
       const size_t tb = timing ? tev(rt->stream) : 0;
-      const int64_t n64 = g64count[L], nlp = gcount[L] - g64count[L];
-      if (n64 > 0) {
-        a.begin = gbegin[L];
-        a.count = n64;
-        a.counter = (unsigned long long *)(db + o_cnt) + 3 * L + 1;
-        const int wg = (int)std::min<int64_t>(n64, gcus);
-        gworkers = std::max(gworkers, wg);
-        int le = dcx_launch_gemm(a, wg, rt->stream);
-        if (le != 0) { fail_hip((hipError_t)le, "gemm launch"); drop(); return -EIO; }
-      }
-      if (nlp > 0) {
-        a.begin = gbegin[L] + n64;
-        a.count = nlp;
-        a.counter = (unsigned long long *)(db + o_cnt) + 3 * L + 2;
-        const int wg = (int)std::min<int64_t>(nlp, gcus);
-        gworkers = std::max(gworkers, wg);
-        int le = dcx_launch_gemm_lowp(a, wg, rt->stream);
-        if (le != 0) { fail_hip((hipError_t)le, "gemm launch"); drop(); return -EIO; }
+      const int64_t n64 = g64count[L], n32 = g32count[L], nlp = gcount[L] - n64 - n32;
+      int64_t begin = gbegin[L];
+      for (int v = 0; v < 3; ++v) {
+        const int64_t cnt = v == 0 ? n64 : v == 1 ? n32 : nlp;
+        if (cnt > 0) {
+          a.begin = begin;
+          a.count = cnt;
+          a.counter = (unsigned long long *)(db + o_cnt) + 4 * L + 1 + v;
+          const int wg = (int)std::min<int64_t>(cnt, gcus);
+          gworkers = std::max(gworkers, wg);
+          const int le = v < 2 ? dcx_launch_gemm(a, wg, v == 0 ? T_F64 : T_F32, rt->stream)
+                               : dcx_launch_gemm_lowp(a, wg, rt->stream);
+          if (le != 0) { fail_hip((hipError_t)le, "gemm launch"); drop(); return -EIO; }
+        }
+        begin += cnt;
       }
       if (timing) {
         const size_t te = tev(rt->stream);

@@ -33,7 +33,7 @@
 #include "runtime_internal.h"
 
 int dcx_submit_potrs_tiles(dc_runtime *rt, const std::vector<dc_handle> &L, int64_t T,
-                           const std::vector<dc_handle> &B);
+                           const std::vector<dc_handle> &B, const std::vector<dc_handle> *V);
 
 namespace {
 
@@ -112,12 +112,12 @@ struct Slot {
   size_t off = 0, bytes = 0;
   // workspace layout (device pointers)
   double *diag = nullptr, *r = nullptr;
-  void *w = nullptr, *s = nullptr;
+  void *w = nullptr, *s = nullptr, *v = nullptr;
   double *hx = nullptr, *hd = nullptr;   // pinned host copies of x and d
   size_t host_cap = 0;
   std::vector<dc_handle> regs;
-  dc_handle hA = 0, hB = 0, hX = 0, hR = 0, hW = 0, hS = 0;
-  std::vector<dc_handle> D, Wt;
+  dc_handle hA = 0, hB = 0, hX = 0, hR = 0, hW = 0, hS = 0, hV = 0, hVl = 0;
+  std::vector<dc_handle> D, Wt, Vall;
   int64_t T = 0;
   int it = 0;
   std::vector<double> prev;
@@ -149,6 +149,7 @@ size_t footprint(const dc_server_config &c, int64_t n, int64_t r, dc_dtype prec)
   b += al256((size_t)n * n * (prec == DC_F64 ? 8 : 4));         // off-diagonal tiles
   if (prec == DC_BF16) b += al256((size_t)n * n * 2);           // BF16 copies
   b += al256((size_t)n * r * 8);                                // residual / correction
+  if (c.tile >= 16) b += al256((size_t)T * c.tile * c.tile * 8);   // inverses
   return b;
 }
 
@@ -166,6 +167,8 @@ void release_slot(dc_server *srv, Slot &s) {
   dc_wait_all(s.rt);
   if (!s.Wt.empty()) dc_matrix_unpartition(s.rt, s.hW);
   s.Wt.clear();
+  if (!s.Vall.empty() && s.hV) dc_matrix_unpartition(s.rt, s.hV);
+  s.Vall.clear();
   for (auto it = s.regs.rbegin(); it != s.regs.rend(); ++it) dc_unregister(s.rt, *it);
   s.regs.clear();
   s.D.clear();
@@ -209,7 +212,7 @@ int solve_into(Slot &s, dc_handle V) {
   int e = 0;
   for (int64_t j = 0; j < tc && !e; ++j) {
     for (int64_t i = 0; i < s.T; ++i) rows[i] = vt[i * tc + j];
-    e = dcx_submit_potrs_tiles(s.rt, L, s.T, rows);
+    e = dcx_submit_potrs_tiles(s.rt, L, s.T, rows, s.v ? &s.Vall : nullptr);
   }
   // the row blocks stay registered until the graph ran; unpartitioning waits
   // for them, so it happens when the step is collected
@@ -236,7 +239,10 @@ int start(dc_server *srv, Slot &s, const Request &q, size_t off, size_t bytes) {
   s.w = base + o; o += al256((size_t)n * n * (q.prec == DC_F64 ? 8 : 4));
   s.s = nullptr;
   if (q.prec == DC_BF16) { s.s = base + o; o += al256((size_t)n * n * 2); }
-  s.r = (double *)(base + o);
+  s.r = (double *)(base + o); o += al256((size_t)n * r * 8);
+  // inverses of the diagonal factors: panel solves and the diagonal steps of
+  // the solves become MFMA products
+  s.v = c.tile >= 16 ? base + o : nullptr;
   if (s.host_cap < (size_t)n * r) {
     if (s.hx) hipHostFree(s.hx);
     if (s.hd) hipHostFree(s.hd);
@@ -254,16 +260,24 @@ int start(dc_server *srv, Slot &s, const Request &q, size_t off, size_t bytes) {
   TRY(reg(s, &s.hW, s.w, n, n, n, q.prec == DC_F64 ? DC_F64 : DC_F32, s.hA));
   s.hS = 0;
   if (s.s) TRY(reg(s, &s.hS, s.s, n, n, n, DC_BF16, s.hA));
+  s.hV = s.hVl = 0;
+  const int64_t last = n - (s.T - 1) * tile;
+  if (s.v && s.T > 1) TRY(reg(s, &s.hV, s.v, (s.T - 1) * tile, tile, tile, DC_F64, s.hA));
+  if (s.v && last >= 16)
+    TRY(reg(s, &s.hVl, (char *)s.v + (size_t)(s.T - 1) * tile * tile * 8, last, last, tile, DC_F64,
+            s.hA));
   s.D.assign(s.T, 0);
   for (int64_t k = 0; k < s.T; ++k) {
     const int64_t nb = std::min(tile, n - k * tile);
     TRY(reg(s, &s.D[k], (char *)s.diag + (size_t)k * tile * tile * 8, nb, nb, tile, DC_F64, s.hA));
   }
   // factor graph
-  std::vector<dc_handle> At(s.T * s.T), W(s.T * s.T), S(s.T * s.T, 0);
+  std::vector<dc_handle> At(s.T * s.T), W(s.T * s.T), S(s.T * s.T, 0),
+      V(s.hV ? s.T - 1 : 0);
   TRY(dc_matrix_partition(s.rt, s.hA, tile, At.data()));
   int e = dc_matrix_partition(s.rt, s.hW, tile, W.data());
   if (!e && s.hS) e = dc_matrix_partition(s.rt, s.hS, tile, S.data());
+  if (!e && s.hV) e = dc_matrix_partition(s.rt, s.hV, tile, V.data());
   auto a = [&](int64_t i, int64_t j) { return At[i * s.T + j]; };
   auto w = [&](int64_t i, int64_t j) { return W[i * s.T + j]; };
   auto sh = [&](int64_t i, int64_t j) { return S[i * s.T + j]; };
@@ -276,10 +290,17 @@ int start(dc_server *srv, Slot &s, const Request &q, size_t off, size_t bytes) {
   for (int64_t k = 0; k < s.T && !e; ++k) {
     const int64_t row0 = k * tile;
     e = submit(s.rt, DC_POTRF, {s.D[k]}, {DC_RW}, 0, &row0, sizeof(row0));
+    const bool inv = s.hV && k + 1 < s.T;
+    if (inv && !e) e = submit(s.rt, DC_TRTRI, {s.D[k], V[k]}, {DC_R, DC_W}, 0);
     for (int64_t i = k + 1; i < s.T && !e; ++i) {
       const int pr = i == k + 1 ? 0 : 1;
-      e = bf ? submit(s.rt, DC_TRSM_CAST, {s.D[k], w(i, k), sh(i, k)}, {DC_R, DC_RW, DC_W}, pr)
-             : submit(s.rt, DC_TRSM, {s.D[k], w(i, k)}, {DC_R, DC_RW}, pr);
+      if (inv)
+        e = bf ? submit(s.rt, DC_TRSM_INV_CAST, {s.D[k], V[k], w(i, k), sh(i, k)},
+                        {DC_R, DC_R, DC_RW, DC_W}, pr)
+               : submit(s.rt, DC_TRSM_INV, {s.D[k], V[k], w(i, k)}, {DC_R, DC_R, DC_RW}, pr);
+      else
+        e = bf ? submit(s.rt, DC_TRSM_CAST, {s.D[k], w(i, k), sh(i, k)}, {DC_R, DC_RW, DC_W}, pr)
+               : submit(s.rt, DC_TRSM, {s.D[k], w(i, k)}, {DC_R, DC_RW}, pr);
     }
     for (int64_t i = k + 1; i < s.T && !e; ++i) {
       const dc_handle xi = bf ? sh(i, k) : w(i, k);
@@ -289,7 +310,9 @@ int start(dc_server *srv, Slot &s, const Request &q, size_t off, size_t bytes) {
                    j == k + 1 ? 1 : 2);
     }
   }
+  if (!e && s.hVl) e = submit(s.rt, DC_TRTRI, {s.D[s.T - 1], s.hVl}, {DC_R, DC_W}, 0);
   if (!e) e = launch(s);
+  if (s.hV) dc_matrix_unpartition(s.rt, s.hV);
   if (s.hS) dc_matrix_unpartition(s.rt, s.hS);
   dc_matrix_unpartition(s.rt, s.hW);
   dc_matrix_unpartition(s.rt, s.hA);
@@ -323,6 +346,11 @@ int step(dc_server *srv, Slot &s) {
       }
       s.Wt.assign(s.T * s.T, 0);
       TRY(dc_matrix_partition(s.rt, s.hW, c.tile, s.Wt.data()));
+      if (s.v) {
+        s.Vall.assign(s.T, 0);
+        if (s.hV) TRY(dc_matrix_partition(s.rt, s.hV, c.tile, s.Vall.data()));
+        s.Vall[s.T - 1] = s.hVl;
+      }
       // x0 = solve(b); then r = b - A x0 and d = solve(r).  Each flush
       // releases the handles it used, so partitions can change between the
       // flushed graphs, which run in stream order.

@@ -27,7 +27,8 @@ dc_handle = ctypes.c_int64
 DC_R, DC_W, DC_RW = 1, 2, 3
 DC_F64, DC_F32, DC_BF16 = 0, 1, 2
 (DC_POTRF, DC_TRSM, DC_SYRK, DC_GEMM, DC_TRSM_L, DC_GEMM_RHS_N, DC_TRSM_LT, DC_GEMM_RHS_T,
- DC_SCAL, DC_CAST, DC_RESID, DC_AXPY, DC_TRSM_CAST, DC_TRTRI, DC_TRSM_INV) = range(15)
+ DC_SCAL, DC_CAST, DC_RESID, DC_AXPY, DC_TRSM_CAST, DC_TRTRI, DC_TRSM_INV,
+ DC_TRSM_INV_CAST, DC_TRSM_L_INV, DC_TRSM_LT_INV) = range(18)
 
 ERRNO = {22: "EINVAL", 2: "ENOENT", 16: "EBUSY", 12: "ENOMEM", 19: "ENODEV", 110: "ETIMEDOUT",
          5: "EIO", 38: "ENOSYS"}

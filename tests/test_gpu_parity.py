@@ -190,6 +190,68 @@ def test_trsm_inv_falls_back_to_substitution(dc, rt, torch_dev, m, nb):
     assert np.array_equal(sub, core.trsm_tile(l0, x))
 
 
+def _with_inverse(dc, rt, torch_dev, l, b, kind):
+    """TRTRI then one task of `kind` (L, W, B) on B; returns B."""
+    torch, dev = torch_dev
+    nb = l.shape[0]
+    tl, tb = _gpu(torch_dev, l), _gpu(torch_dev, b)
+    tw = torch.zeros((nb, nb), dtype=torch.float64, device=dev)
+    hl, hw, hb = rt.register_tensor(tl), rt.register_tensor(tw), rt.register_tensor(tb)
+    rt.dc_task_submit(dc.DC_TRTRI, [hl, hw], [dc.DC_R, dc.DC_W])
+    rt.dc_task_submit(kind, [hl, hw, hb], [dc.DC_R, dc.DC_R, dc.DC_RW])
+    rt.dc_wait_all()
+    for h in (hl, hw, hb):
+        rt.dc_unregister(h)
+    return tb.cpu().numpy()
+
+
+@pytest.mark.parametrize("nb,r", [(512, 1), (512, 16), (100, 3), (16, 1), (256, 20), (37, 40)])
+def test_solve_steps_through_inverse(dc, rt, torch_dev, nb, r):
+    l = np.linalg.cholesky(inputs.spd_uniform(nb, 2 * nb + r))
+    assert _amp(l) <= 1024
+    bm = np.random.default_rng(nb * r).standard_normal((nb, r))
+    tol = 64 * nb * U * np.linalg.cond(l)
+    got = _with_inverse(dc, rt, torch_dev, l, bm, dc.DC_TRSM_L_INV)
+    ref = core.trsm_left_tile(l, bm)
+    assert np.abs(got - ref).max() <= tol * np.abs(ref).max()
+    got = _with_inverse(dc, rt, torch_dev, l, bm, dc.DC_TRSM_LT_INV)
+    ref = core.trsm_left_t_tile(l, bm)
+    assert np.abs(got - ref).max() <= tol * np.abs(ref).max()
+
+
+def test_solve_steps_through_inverse_fall_back(dc, rt, torch_dev):
+    nb, r = 96, 5
+    _, l0 = inputs.integer_factor(nb, 12)
+    assert _amp(l0) > 1024
+    x = np.random.default_rng(3).integers(-3, 4, (nb, r)).astype(np.float64)
+    got = _with_inverse(dc, rt, torch_dev, l0, l0 @ x, dc.DC_TRSM_L_INV)
+    assert np.array_equal(got, x)
+    got = _with_inverse(dc, rt, torch_dev, l0, l0.T @ x, dc.DC_TRSM_LT_INV)
+    assert np.array_equal(got, x)
+
+
+def test_trsm_inv_cast_writes_bf16_copy(dc, rt, torch_dev):
+    import torch
+    m, nb = 70, 256
+    l = np.linalg.cholesky(inputs.spd_uniform(nb, 5))
+    x = np.random.default_rng(9).standard_normal((m, nb)).astype(np.float32)
+    _, dev = torch_dev
+    tl, tx = _gpu(torch_dev, l), _gpu(torch_dev, x)
+    tw = torch.zeros((nb, nb), dtype=torch.float64, device=dev)
+    ts = torch.zeros((m, nb), dtype=torch.bfloat16, device=dev)
+    hs = [rt.register_tensor(t) for t in (tl, tw, tx, ts)]
+    rt.dc_task_submit(dc.DC_TRTRI, hs[:2], [dc.DC_R, dc.DC_W])
+    rt.dc_task_submit(dc.DC_TRSM_INV_CAST, hs, [dc.DC_R, dc.DC_R, dc.DC_RW, dc.DC_W])
+    rt.dc_wait_all()
+    for h in hs:
+        rt.dc_unregister(h)
+    got = tx.cpu()
+    assert torch.equal(ts.cpu(), got.to(torch.bfloat16))
+    ref = core.trsm_tile(l, x.astype(np.float64))
+    tol = 64 * nb * U * np.linalg.cond(l) + 2.0 ** -24
+    assert np.abs(got.numpy().astype(np.float64) - ref).max() <= tol * np.abs(ref).max()
+
+
 @pytest.mark.parametrize("nb", [1, 16, 37, 128, 512])
 def test_potrf_task(dc, rt, torch_dev, nb):
     a = inputs.spd_normal(nb, nb, 0.1)
