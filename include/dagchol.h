@@ -107,11 +107,12 @@ typedef enum { DC_F64 = 0, DC_F32 = 1, DC_BF16 = 2 } dc_dtype;
  *                                   X FP64 or FP32.
  *   DC_TRSM_INV_CAST (L:R, W:R, X:RW, S:W)  TRSM_INV on an FP32 tile X that
  *                                   also writes S = BF16(X).
- *   DC_TRSM_L_INV  (L:R, W:R, B:RW) B <- L^{-1} B computed as W B, and
- *   DC_TRSM_LT_INV (L:R, W:R, B:RW) B <- L^{-T} B computed as W^T B, with W
- *                                   from DC_TRTRI of the same L (FP64 L, W
- *                                   and B, order 16..512); both fall back to
- *                                   substitution like DC_TRSM_INV.
+ *   DC_TRSM_L_INV  (L:R, W:R, S:R, D:W)  D <- L^{-1} S computed as W S, and
+ *   DC_TRSM_LT_INV (L:R, W:R, S:R, D:W)  D <- L^{-T} S computed as W^T S,
+ *                                   out of place (S and D distinct nb x r),
+ *                                   with W from DC_TRTRI of the same L (FP64
+ *                                   L, W, S and D, order 16..512); both fall
+ *                                   back to substitution like DC_TRSM_INV.
  * Precisions (the dtypes of the handles select the kernel):
  *   POTRF: FP64.  TRSM: L FP64, X FP64 or FP32 (FP64 arithmetic, FP32 tiles
  *   rounded on store).  SYRK/GEMM: FP64 inputs update FP64 tiles with FP64

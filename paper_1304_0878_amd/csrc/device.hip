@@ -264,41 +264,22 @@ __device__ __forceinline__ void run_trsm(const TaskDesc &d, int unit, double *ld
 // accuracy.
 constexpr double INV_LIMIT = 1024.0;
 
-// The product, shared with the diagonal steps of the solves (MODE):
-//   INV_PANEL  X (m x nb) rows r0.. <- X W^T          (TRSM_INV, W = L^{-1})
-//   INV_FWD    B (nb x r) cols c0.. <- W B = L^{-1} B  (TRSM_L_INV)
-//   INV_BWD    B (nb x r) cols c0.. <- W^T B = L^{-T} B (TRSM_LT_INV)
-// In the solve modes the unit's 16 right-hand-side columns are staged as
-// the 16 rows of X (X = B^T), so out[c][i] = sum_k X[c][k] Wop[i][k] with
-// Wop = W (forward, k <= i) or W^T (backward, k >= i).  Backward reads W
-// by rows k, 16 lanes taking 16 consecutive columns i.
-constexpr int INV_PANEL = 0, INV_FWD = 1, INV_BWD = 2;
-
-template <bool FULL, int MODE>
+template <bool FULL>
 __device__ __forceinline__ void trsm_inv_product(const TaskDesc &d, int unit, double *lds) {
-  const bool solve = MODE != INV_PANEL;
-  const int nb = solve ? d.m : d.n;
+  const int nb = d.n;
   const int nb16 = (nb + 15) / 16;
   const int r0 = unit * TRSM_ROWS;
-  // X rows: rows of X (panel), or right-hand-side columns (solves)
-  const int rows = min(TRSM_ROWS, (solve ? d.n : d.m) - r0);
+  const int rows = min(TRSM_ROWS, d.m - r0);
   const int XS = panel_stride(nb);
   const gdouble *W = (const gdouble *)d.a;
   const int64_t ldw = d.lda;
   const int64_t ldc = d.ldc;
-  const bool x32 = !solve && d.tc == T_F32;
+  const bool x32 = d.tc == T_F32;
   double *Xs = lds;
-  if (solve) {
-    const gdouble *Bm = (const gdouble *)d.c;
-    for (int idx = threadIdx.x; idx < TRSM_ROWS * nb; idx += NT) {
-      const int k = idx >> 4, c = idx & 15;
-      Xs[c * XS + k] = c < rows ? Bm[(int64_t)k * ldc + r0 + c] : 0.0;
-    }
-  } else if (x32) {
+  if (x32)
     stage16<float>(Xs, XS, (gfloat *)d.c + (int64_t)r0 * ldc, ldc, rows, nb);
-  } else {
+  else
     stage16<double>(Xs, XS, (gdouble *)d.c + (int64_t)r0 * ldc, ldc, rows, nb);
-  }
   __syncthreads();
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int l16 = lane & 15, kq = lane >> 4;
@@ -306,33 +287,27 @@ __device__ __forceinline__ void trsm_inv_product(const TaskDesc &d, int unit, do
   dvec4 acc[8];
 #pragma unroll
   for (int i = 0; i < 8; ++i) acc[i] = dvec4{0.0, 0.0, 0.0, 0.0};
-  // block b takes chunk kc when the chunk meets the triangle of Wop
-  auto active = [&](int b, int kc) { return b < nb16 && (MODE == INV_BWD ? b <= kc : b >= kc); };
-  // B operand of block b, chunk kc, step s: Wop[16b + l16][16kc + 4kq + s]
+  // B operand of block b, chunk kc: W[16b + l16][16kc + 4kq + s], s < 4
   auto wload = [&](int kc, double (&v)[8][4]) {
     const int k = 16 * kc + 4 * kq;
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
       const int b = w + 4 * i;
-      if (active(b, kc)) {
-        const int col = 16 * b + l16;   // output column i
-        if (MODE == INV_BWD) {
-#pragma unroll
-          for (int s = 0; s < 4; ++s)
-            v[i][s] = (FULL || (col < nb && k + s < nb)) ? W[(int64_t)(k + s) * ldw + col] : 0.0;
-        } else if (FULL) {
-          const gdvec2 *p = (const gdvec2 *)(W + (int64_t)col * ldw + k);
+      if (b >= kc && b < nb16) {
+        const int row = 16 * b + l16;
+        if (FULL) {
+          const gdvec2 *p = (const gdvec2 *)(W + (int64_t)row * ldw + k);
           const dvec2 x0 = p[0], x1 = p[1];
           v[i][0] = x0[0]; v[i][1] = x0[1]; v[i][2] = x1[0]; v[i][3] = x1[1];
         } else {
 #pragma unroll
           for (int s = 0; s < 4; ++s)
-            v[i][s] = (col < nb && k + s < nb) ? W[(int64_t)col * ldw + k + s] : 0.0;
+            v[i][s] = (row < nb && k + s < nb) ? W[(int64_t)row * ldw + k + s] : 0.0;
         }
-        if (b == kc) {   // diagonal chunk: only the triangle of W is read
+        if (b == kc) {   // diagonal chunk: only k <= row is part of W
 #pragma unroll
           for (int s = 0; s < 4; ++s)
-            if (MODE == INV_BWD ? 4 * kq + s < l16 : 4 * kq + s > l16) v[i][s] = 0.0;
+            if (4 * kq + s > l16) v[i][s] = 0.0;
         }
       }
     }
@@ -345,7 +320,7 @@ __device__ __forceinline__ void trsm_inv_product(const TaskDesc &d, int unit, do
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
       const int b = w + 4 * i;
-      if (active(b, kc)) {
+      if (b >= kc && b < nb16) {
 #pragma unroll
         for (int s = 0; s < 4; ++s)
           acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], v[i][s], acc[i], 0, 0, 0);
@@ -372,9 +347,7 @@ __device__ __forceinline__ void trsm_inv_product(const TaskDesc &d, int unit, do
       for (int e = 0; e < 4; ++e) {
         const int row = kq + 4 * e;
         if (row < rows) {
-          if (solve) {
-            ((gdouble *)d.c)[(int64_t)col * ldc + r0 + row] = acc[i][e];
-          } else if (x32) {
+          if (x32) {
             const float v = (float)acc[i][e];
             ((gfloat *)d.c)[(int64_t)(r0 + row) * ldc + col] = v;
             if (d.d) ((gbf16 *)d.d)[(int64_t)(r0 + row) * d.ldd + col] = (__bf16)v;
@@ -383,6 +356,99 @@ __device__ __forceinline__ void trsm_inv_product(const TaskDesc &d, int unit, do
           }
         }
       }
+    }
+  }
+}
+
+// Diagonal step of a solve through W = L^{-1}, out of place: D <- W S
+// (forward) or D <- W^T S (backward), S and D nb x r.  A unit is 64 rows of
+// D (one 16-row block per wave) by 16 columns, so a step spreads over
+// nb/64 x r/16 workgroups that stream disjoint rows (forward) or columns
+// (backward) of W.  The 16 columns of S are staged as the 16 rows of
+// X = S^T over the K range the unit's rows need (k <= i forward, k >= i
+// backward); out[c][i] = sum_k X[c][k] Wop[i][k], Wop = W or W^T, with
+// 16x16x4 FP64 MFMA.
+template <bool FULL, bool FWD>
+__device__ __forceinline__ void solve_inv_product(const TaskDesc &d, int unit, double *lds) {
+  const int nb = d.m, r = d.n;
+  const int nb16 = (nb + 15) / 16;
+  const int ncc = (r + 15) / 16;
+  const int rb = unit / ncc, c0 = 16 * (unit - rb * ncc);
+  const int rc = min(16, r - c0);
+  const int XS = panel_stride(nb);
+  const gdouble *W = (const gdouble *)d.a;
+  const int64_t ldw = d.lda;
+  const gdouble *Sm = (const gdouble *)d.c;
+  gdouble *Dm = (gdouble *)d.d;
+  // chunks the unit's four blocks need
+  static_assert(SOLVE_INV_ROWS == 4 * 16, "one 16-row block per wave");
+  const int b0 = 4 * rb;
+  const int kc_lo = FWD ? 0 : b0;
+  const int kc_hi = FWD ? min(nb16, b0 + 4) : nb16;   // exclusive
+  const int k_lo = 16 * kc_lo, k_hi = min(nb, 16 * kc_hi);
+  double *Xs = lds;
+  for (int idx = threadIdx.x; idx < 16 * (k_hi - k_lo); idx += NT) {
+    const int k = k_lo + (idx >> 4), c = idx & 15;
+    Xs[c * XS + k] = c < rc ? Sm[(int64_t)k * d.ldc + c0 + c] : 0.0;
+  }
+  __syncthreads();
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int l16 = lane & 15, kq = lane >> 4;
+  const int b = b0 + w;                      // this wave's block of rows
+  const int col = 16 * b + l16;              // output row i of this lane
+  typedef double dvec4 __attribute__((ext_vector_type(4)));
+  dvec4 acc = dvec4{0.0, 0.0, 0.0, 0.0};
+  auto active = [&](int kc) { return b < nb16 && (FWD ? kc <= b : kc >= b); };
+  auto wload = [&](int kc, double (&v)[4]) {
+    if (!active(kc)) return;
+    const int k = 16 * kc + 4 * kq;
+    if (!FWD) {
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+        v[s] = (FULL || (col < nb && k + s < nb)) ? W[(int64_t)(k + s) * ldw + col] : 0.0;
+    } else if (FULL) {
+      const gdvec2 *p = (const gdvec2 *)(W + (int64_t)col * ldw + k);
+      const dvec2 x0 = p[0], x1 = p[1];
+      v[0] = x0[0]; v[1] = x0[1]; v[2] = x1[0]; v[3] = x1[1];
+    } else {
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+        v[s] = (col < nb && k + s < nb) ? W[(int64_t)col * ldw + k + s] : 0.0;
+    }
+    if (kc == b) {   // diagonal chunk: only the triangle of W is read
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+        if (FWD ? 4 * kq + s > l16 : 4 * kq + s < l16) v[s] = 0.0;
+    }
+  };
+  auto chunk = [&](int kc, const double (&v)[4]) {
+    if (!active(kc)) return;
+    const int k = 16 * kc + 4 * kq;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const double a = (FULL || k + s < nb) ? Xs[l16 * XS + k + s] : 0.0;
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, v[s], acc, 0, 0, 0);
+    }
+  };
+  // up to four chunks of loads in flight ahead of the multiplications
+  double v0[4] = {0, 0, 0, 0}, v1[4] = {0, 0, 0, 0}, v2[4] = {0, 0, 0, 0}, v3[4] = {0, 0, 0, 0};
+  for (int kc = kc_lo; kc < kc_hi; kc += 4) {
+    wload(kc, v0);
+    if (kc + 1 < kc_hi) wload(kc + 1, v1);
+    if (kc + 2 < kc_hi) wload(kc + 2, v2);
+    if (kc + 3 < kc_hi) wload(kc + 3, v3);
+    chunk(kc, v0);
+    if (kc + 1 < kc_hi) chunk(kc + 1, v1);
+    if (kc + 2 < kc_hi) chunk(kc + 2, v2);
+    if (kc + 3 < kc_hi) chunk(kc + 3, v3);
+  }
+  // result element e of lane l: row (right-hand side) l/16 + 4e, column
+  // (row i of D) l%16 of the block
+  if (b < nb16 && col < nb) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int c = kq + 4 * e;
+      if (c < rc) Dm[(int64_t)col * d.ldd + c0 + c] = acc[e];
     }
   }
 }
@@ -406,9 +472,9 @@ __device__ __forceinline__ void run_trsm_inv(const TaskDesc &d, int unit, double
   if (!inverse_usable(d, d.n))
     trsm_core<false>(d, unit, lds, (const gdouble *)d.b, d.ldb);
   else if (inverse_full(d, d.n))
-    trsm_inv_product<true, INV_PANEL>(d, unit, lds);
+    trsm_inv_product<true>(d, unit, lds);
   else
-    trsm_inv_product<false, INV_PANEL>(d, unit, lds);
+    trsm_inv_product<false>(d, unit, lds);
 }
 
 // ----------------------------------------------------------------- POTRF
@@ -720,9 +786,12 @@ __device__ __forceinline__ void trsm_l_pass(const TaskDesc &d, double *lds, int 
     solve_block<true>(Bs, part, Ljj, i0, h, rc);
     __syncthreads();
   }
+  // in place, or into d.d (the out-of-place diagonal steps' fallback)
+  gdouble *Bo = d.d ? (gdouble *)d.d : Bm;
+  const int64_t ldo = d.d ? d.ldd : ldb;
   for (int idx = tid; idx < nb * CW; idx += NT) {
     const int i = idx / CW, c = idx % CW;
-    if (c < rc) Bm[(int64_t)i * ldb + c0 + c] = Bs[i * BSS + c];
+    if (c < rc) Bo[(int64_t)i * ldo + c0 + c] = Bs[i * BSS + c];
   }
   __syncthreads();
 }
@@ -797,9 +866,12 @@ __device__ __forceinline__ void trsm_lt_pass(const TaskDesc &d, double *lds, int
     solve_block<false>(Bs, part, Ljj, i0, h, rc);
     __syncthreads();
   }
+  // in place, or into d.d (the out-of-place diagonal steps' fallback)
+  gdouble *Bo = d.d ? (gdouble *)d.d : Bm;
+  const int64_t ldo = d.d ? d.ldd : ldb;
   for (int idx = tid; idx < nb * CW; idx += NT) {
     const int i = idx / CW, c = idx % CW;
-    if (c < rc) Bm[(int64_t)i * ldb + c0 + c] = Bs[i * BSS + c];
+    if (c < rc) Bo[(int64_t)i * ldo + c0 + c] = Bs[i * BSS + c];
   }
   __syncthreads();
 }
@@ -814,11 +886,11 @@ __device__ __forceinline__ void run_trsm_lt(const TaskDesc &d, double *lds) {
   }
 }
 
-// Diagonal step of a solve through W = L^{-1} (TRSM_L_INV, TRSM_LT_INV):
-// unit u takes right-hand-side columns 16u..16u+15.  With an ill-conditioned
-// L (see TRSM_INV) unit 0 solves all columns by substitution with L and the
-// other units do nothing.
-template <int MODE>
+// Diagonal step of a solve through W = L^{-1} (TRSM_L_INV, TRSM_LT_INV),
+// D <- L^{-1} S or L^{-T} S.  With an ill-conditioned L (see TRSM_INV) unit 0
+// solves all columns by substitution with L, reading S and writing D, and
+// the other units do nothing.
+template <bool FWD>
 __device__ __forceinline__ void run_trsm_l_inv(const TaskDesc &d, int unit, double *lds) {
   if (!inverse_usable(d, d.m)) {
     if (unit == 0) {
@@ -826,14 +898,14 @@ __device__ __forceinline__ void run_trsm_l_inv(const TaskDesc &d, int unit, doub
       dd.a = d.b;
       dd.lda = d.ldb;
       dd.ta = T_F64;
-      if (MODE == INV_FWD) run_trsm_l<double>(dd, lds); else run_trsm_lt<double>(dd, lds);
+      if (FWD) run_trsm_l<double>(dd, lds); else run_trsm_lt<double>(dd, lds);
     }
     return;
   }
   if (inverse_full(d, d.m))
-    trsm_inv_product<true, MODE>(d, unit, lds);
+    solve_inv_product<true, FWD>(d, unit, lds);
   else
-    trsm_inv_product<false, MODE>(d, unit, lds);
+    solve_inv_product<false, FWD>(d, unit, lds);
 }
 
 // B_I (m x r) -= L_IK (m x kb) Y_K (kb x r); unit = 16 rows, thread (row,
@@ -1024,6 +1096,8 @@ __device__ __forceinline__ void add2(double &s, double &c, double s2, double c2)
 // to FP64 roundoff rather than to cond(A) times it.  Part 1: each wave takes
 // 16 rows, lanes split the stored row (j <= i); part 2: lane = row, waves
 // split the column below the diagonal (j > i), read coalesced.
+constexpr int RB = 4;   // residual terms per lane in flight
+
 __device__ __forceinline__ void run_resid(const TaskDesc &d, int unit, double *lds) {
 #pragma clang fp contract(off)
   const gdouble *A = (const gdouble *)d.a;
@@ -1044,18 +1118,32 @@ __device__ __forceinline__ void run_resid(const TaskDesc &d, int unit, double *l
 #pragma unroll
       for (int k = 0; k < 4; ++k) s[k] = c[k] = 0.0;
       if (i < n) {
+        // RB terms per lane loaded before they are accumulated (same order
+        // of accumulation, more loads in flight)
         const gdouble *ar = A + (int64_t)i * d.lda;
-        for (int j = lane; j <= i; j += 64) {
-          const double av = ar[j];
-          const gdouble *xp = X + (int64_t)j * d.ldb + c0;
+        for (int jb = lane; jb <= i; jb += RB * 64) {
+          double av[RB], xv[RB][4];
 #pragma unroll
-          for (int k = 0; k < 4; ++k)
-            if (c0 + k < r) {
-              double p, e, t;
-              two_prod(av, xp[k], p, e);
-              two_sum(s[k], p, s[k], t);
-              c[k] = c[k] + (t + e);
+          for (int u = 0; u < RB; ++u) {
+            const int j = jb + 64 * u;
+            av[u] = j <= i ? ar[j] : 0.0;
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+              xv[u][k] = (j <= i && c0 + k < r) ? X[(int64_t)j * d.ldb + c0 + k] : 0.0;
+          }
+#pragma unroll
+          for (int u = 0; u < RB; ++u) {
+            if (jb + 64 * u <= i) {
+#pragma unroll
+              for (int k = 0; k < 4; ++k)
+                if (c0 + k < r) {
+                  double p, e, t;
+                  two_prod(av[u], xv[u][k], p, e);
+                  two_sum(s[k], p, s[k], t);
+                  c[k] = c[k] + (t + e);
+                }
             }
+          }
         }
       }
 #pragma unroll
@@ -1078,18 +1166,30 @@ __device__ __forceinline__ void run_resid(const TaskDesc &d, int unit, double *l
 #pragma unroll
       for (int k = 0; k < 4; ++k) s[k] = c[k] = 0.0;
       if (i < n) {
-        for (int j = i0 + 1 + w; j < n; j += 4) {
-          if (j > i) {
-            const double av = A[(int64_t)j * d.lda + i];
-            const gdouble *xp = X + (int64_t)j * d.ldb + c0;
+        for (int jb = i0 + 1 + w; jb < n; jb += RB * 4) {
+          double av[RB], xv[RB][4];
+#pragma unroll
+          for (int u = 0; u < RB; ++u) {
+            const int j = jb + 4 * u;
+            const bool ok = j < n && j > i;
+            av[u] = ok ? A[(int64_t)j * d.lda + i] : 0.0;
 #pragma unroll
             for (int k = 0; k < 4; ++k)
-              if (c0 + k < r) {
-                double p, e, t;
-                two_prod(av, xp[k], p, e);
-                two_sum(s[k], p, s[k], t);
-                c[k] = c[k] + (t + e);
-              }
+              xv[u][k] = (ok && c0 + k < r) ? X[(int64_t)j * d.ldb + c0 + k] : 0.0;
+          }
+#pragma unroll
+          for (int u = 0; u < RB; ++u) {
+            const int j = jb + 4 * u;
+            if (j < n && j > i) {
+#pragma unroll
+              for (int k = 0; k < 4; ++k)
+                if (c0 + k < r) {
+                  double p, e, t;
+                  two_prod(av[u], xv[u][k], p, e);
+                  two_sum(s[k], p, s[k], t);
+                  c[k] = c[k] + (t + e);
+                }
+            }
           }
         }
       }
@@ -1158,8 +1258,8 @@ __global__ void __launch_bounds__(NT, 1) dc_level_kernel(LevelArgs A) {
         case K_TRSM: case K_TRSM_CAST: run_trsm(d, u, lds); break;
         case K_TRTRI: trsm_core<true>(d, u, lds, (const gdouble *)d.a, d.lda); break;
         case K_TRSM_INV: case K_TRSM_INV_CAST: run_trsm_inv(d, u, lds); break;
-        case K_TRSM_L_INV: run_trsm_l_inv<INV_FWD>(d, u, lds); break;
-        case K_TRSM_LT_INV: run_trsm_l_inv<INV_BWD>(d, u, lds); break;
+        case K_TRSM_L_INV: run_trsm_l_inv<true>(d, u, lds); break;
+        case K_TRSM_LT_INV: run_trsm_l_inv<false>(d, u, lds); break;
         case K_POTRF: {
           const int bad = run_potrf(d, lds);
           if (bad && tid == 0 && d.matrix >= 0) {

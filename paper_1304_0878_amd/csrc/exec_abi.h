@@ -51,6 +51,9 @@ constexpr int BSS = 17;
 __host__ __device__ constexpr int solve_lds_doubles(int nb) {
   return (nb + 15) / 16 * 16 * BSS + 16 * 16 * 16 + 16 * 16 + 16 * 17;
 }
+// Rows of D one unit of an out-of-place diagonal solve step (TRSM_L_INV,
+// TRSM_LT_INV) produces.
+constexpr int SOLVE_INV_ROWS = 64;
 // Rows of a right-hand-side update unit (GEMM_RHS_N, GEMM_RHS_T) and its LDS.
 constexpr int RHS_ROWS = 16;
 constexpr int RHS_LDS_DOUBLES = 16 * 16 * 8;

@@ -100,31 +100,52 @@ int dcx_submit_potrf_tiles(dc_runtime *rt, const std::vector<dc_handle> &A, int6
   return 0;
 }
 
+static int submit4(dc_runtime *rt, dc_kind k, dc_handle a, dc_handle c, dc_handle e,
+                   dc_handle f, int prio) {
+  dc_handle b[4] = {a, c, e, f};
+  dc_mode m[4] = {DC_R, DC_R, DC_R, DC_W};
+  return dc_task_submit(rt, k, 4, b, m, nullptr, 0, prio);
+}
+
 // Forward then backward sweep on partitioned L tiles and RHS row blocks.
-// With V (the inverses of the diagonal factors; 0 where there is none) the
-// diagonal steps are products with them (TRSM_L_INV, TRSM_LT_INV).
+// With V (the inverses of all diagonal factors) and Y (row blocks of a
+// scratch of B's shape) the diagonal steps are out-of-place products with
+// the inverses: forward B_k -> Y_k with the updates reading Y_k, backward
+// Y_k -> B_k with the updates of Y_i reading B_k; the solution ends in B.
 int dcx_submit_potrs_tiles(dc_runtime *rt, const std::vector<dc_handle> &L, int64_t T,
-                           const std::vector<dc_handle> &B, const std::vector<dc_handle> *V) {
+                           const std::vector<dc_handle> &B, const std::vector<dc_handle> *V,
+                           const std::vector<dc_handle> *Y) {
   auto at = [&](int64_t i, int64_t j) { return L[i * T + j]; };
-  auto inv = [&](int64_t k) { return V && (*V)[k] != 0; };
+  if (V && Y) {
+    for (int64_t k = 0; k < T; ++k) {
+      TRY(submit4(rt, DC_TRSM_L_INV, at(k, k), (*V)[k], B[k], (*Y)[k], 0));
+      for (int64_t i = k + 1; i < T; ++i)
+        TRY(submit3(rt, DC_GEMM_RHS_N, at(i, k), DC_R, (*Y)[k], DC_R, B[i], DC_RW,
+                    i == k + 1 ? 0 : 1));
+    }
+    for (int64_t k = T - 1; k >= 0; --k) {
+      TRY(submit4(rt, DC_TRSM_LT_INV, at(k, k), (*V)[k], (*Y)[k], B[k], 0));
+      for (int64_t i = k - 1; i >= 0; --i)
+        TRY(submit3(rt, DC_GEMM_RHS_T, at(k, i), DC_R, B[k], DC_R, (*Y)[i], DC_RW,
+                    i == k - 1 ? 0 : 1));
+    }
+    return 0;
+  }
   for (int64_t k = 0; k < T; ++k) {
-    if (inv(k))
-      TRY(submit3(rt, DC_TRSM_L_INV, at(k, k), DC_R, (*V)[k], DC_R, B[k], DC_RW, 0));
-    else
-      TRY(submit2(rt, DC_TRSM_L, at(k, k), DC_R, B[k], DC_RW, 0));
+    TRY(submit2(rt, DC_TRSM_L, at(k, k), DC_R, B[k], DC_RW, 0));
     for (int64_t i = k + 1; i < T; ++i)
       TRY(submit3(rt, DC_GEMM_RHS_N, at(i, k), DC_R, B[k], DC_R, B[i], DC_RW, i == k + 1 ? 0 : 1));
   }
   for (int64_t k = T - 1; k >= 0; --k) {
-    if (inv(k))
-      TRY(submit3(rt, DC_TRSM_LT_INV, at(k, k), DC_R, (*V)[k], DC_R, B[k], DC_RW, 0));
-    else
-      TRY(submit2(rt, DC_TRSM_LT, at(k, k), DC_R, B[k], DC_RW, 0));
+    TRY(submit2(rt, DC_TRSM_LT, at(k, k), DC_R, B[k], DC_RW, 0));
     for (int64_t i = k - 1; i >= 0; --i)
       TRY(submit3(rt, DC_GEMM_RHS_T, at(k, i), DC_R, B[k], DC_R, B[i], DC_RW, i == k - 1 ? 0 : 1));
   }
   return 0;
 }
+
+// Order of the last diagonal tile.
+static int64_t last_tile_order(int64_t n, int64_t tile) { return n - (n - 1) / tile * tile; }
 
 // Grows the runtime's inverse workspace to at least `bytes`; the previous
 // contents are not kept.
@@ -195,20 +216,24 @@ extern "C" int dc_potrs(dc_runtime *rt, dc_handle L, dc_handle B, int64_t tile) 
   const int64_t n = pl->rows;
   const int64_t T = (n + tile - 1) / tile;
   const int64_t last = n - (T - 1) * tile;
-  // inverses of the diagonal factors (tiles of order >= 16): TRTRI for all
-  // of them first, in parallel, then products in place of the diagonal
-  // substitutions of both sweeps
-  const bool inv = tile >= 16 && rt->cfg.device >= 0;
-  dc_handle hw = 0, hl = 0;
-  Tiles tw;
+  // inverses of the diagonal factors (all of order >= 16): TRTRI for all of
+  // them first, in parallel, then out-of-place products instead of the
+  // diagonal substitutions of both sweeps, through a scratch Y of B's shape
+  const int64_t r = pb->cols;
+  const bool inv = tile >= 16 && last_tile_order(n, tile) >= 16 && rt->cfg.device >= 0;
+  dc_handle hw = 0, hl = 0, hy = 0;
+  Tiles tw, ty;
   std::vector<dc_handle> V;
   int e = 0;
   if (inv) {
-    TRY(inv_workspace(rt, T * tile * tile * 8));
+    const int64_t wbytes = T * tile * tile * 8;
+    TRY(inv_workspace(rt, wbytes + n * r * 8));
+    TRY(dc_matrix_register(rt, &hy, (char *)rt->inv_ws + wbytes, n, r, r, DC_F64));
+    e = ty.open(rt, hy, tile);
     V.assign(T, 0);
-    if (T > 1) {
-      TRY(dc_matrix_register(rt, &hw, rt->inv_ws, (T - 1) * tile, tile, tile, DC_F64));
-      e = tw.open(rt, hw, tile);
+    if (T > 1 && !e) {
+      e = dc_matrix_register(rt, &hw, rt->inv_ws, (T - 1) * tile, tile, tile, DC_F64);
+      if (!e) e = tw.open(rt, hw, tile);
       for (int64_t k = 0; k + 1 < T && !e; ++k) V[k] = tw.at(k, 0);
     }
     if (!e && last >= 16)
@@ -223,17 +248,22 @@ extern "C" int dc_potrs(dc_runtime *rt, dc_handle L, dc_handle B, int64_t tile) 
     for (int64_t k = 0; k < T && inv && !e; ++k)
       if (V[k]) e = submit2(rt, DC_TRTRI, tl.at(k, k), DC_R, V[k], DC_W, 0);
     // each column block of B is an independent right-hand-side group
-    std::vector<dc_handle> rows(tl.tr);
+    std::vector<dc_handle> rows(tl.tr), yrows(tl.tr);
     for (int64_t j = 0; j < tb.tc && !e; ++j) {
-      for (int64_t i = 0; i < tl.tr; ++i) rows[i] = tb.at(i, j);
-      e = dcx_submit_potrs_tiles(rt, tl.ids, tl.tr, rows, inv ? &V : nullptr);
+      for (int64_t i = 0; i < tl.tr; ++i) {
+        rows[i] = tb.at(i, j);
+        if (inv) yrows[i] = ty.at(i, j);
+      }
+      e = dcx_submit_potrs_tiles(rt, tl.ids, tl.tr, rows, inv ? &V : nullptr,
+                                 inv ? &yrows : nullptr);
     }
     if (e) dcx_discard_pending(rt);
     else e = dc_wait_all(rt);
   }
   tw.close();
-  if (hw) { const int e2 = dc_unregister(rt, hw); if (!e) e = e2; }
-  if (hl) { const int e2 = dc_unregister(rt, hl); if (!e) e = e2; }
+  ty.close();
+  for (dc_handle h : {hw, hl, hy})
+    if (h) { const int e2 = dc_unregister(rt, h); if (!e) e = e2; }
   return e;
 }
 
@@ -272,7 +302,7 @@ extern "C" int dc_potrf_batched(dc_runtime *rt, int64_t count, const dc_handle *
       std::vector<dc_handle> rows(ta[i].tr);
       for (int64_t j = 0; j < tb[i].tc && !err; ++j) {
         for (int64_t r = 0; r < ta[i].tr; ++r) rows[r] = tb[i].at(r, j);
-        err = dcx_submit_potrs_tiles(rt, ta[i].ids, ta[i].tr, rows, nullptr);
+        err = dcx_submit_potrs_tiles(rt, ta[i].ids, ta[i].tr, rows, nullptr, nullptr);
       }
     }
   }

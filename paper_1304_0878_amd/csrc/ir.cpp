@@ -21,7 +21,8 @@
 int dcx_submit_potrf_tiles(dc_runtime *rt, const std::vector<dc_handle> &A, int64_t T,
                            const std::vector<dc_handle> *W);
 int dcx_submit_potrs_tiles(dc_runtime *rt, const std::vector<dc_handle> &L, int64_t T,
-                           const std::vector<dc_handle> &B, const std::vector<dc_handle> *V);
+                           const std::vector<dc_handle> &B, const std::vector<dc_handle> *V,
+                           const std::vector<dc_handle> *Y);
 
 namespace {
 
@@ -175,10 +176,11 @@ extern "C" int dc_posv_ir(dc_runtime *rt, dc_handle A, dc_handle B, dc_handle X,
     const size_t o_r = al(o_s + (prec == DC_BF16 ? (size_t)n * n * 2 : 0));
     // inverses of the diagonal factors: panel solves and the diagonal steps
     // of every solve become MFMA products
-    const bool inv = tile >= 16;
     const int64_t nlast = n - (T - 1) * tile;
+    const bool inv = tile >= 16 && nlast >= 16;
     const size_t o_v = al(o_r + (size_t)n * r * 8);
-    const size_t total = al(o_v + (inv ? (size_t)T * tile * tile * 8 : 0));
+    const size_t o_y = al(o_v + (inv ? (size_t)T * tile * tile * 8 : 0));   // solve scratch
+    const size_t total = al(o_y + (inv ? (size_t)n * r * 8 : 0));
     TRY(ws.get(total));
     char *base = (char *)ws.ptr;
     Regs regs(rt);
@@ -186,7 +188,8 @@ extern "C" int dc_posv_ir(dc_runtime *rt, dc_handle A, dc_handle B, dc_handle X,
     TRY(regs.mat(&hW, base + o_w, n, n, n, prec == DC_F64 ? DC_F64 : DC_F32, A));
     if (prec == DC_BF16) TRY(regs.mat(&hS, base + o_s, n, n, n, DC_BF16, A));
     TRY(regs.mat(&hR, base + o_r, n, r, r, DC_F64, 0));
-    dc_handle hV = 0, hVl = 0;   // tiles 0..T-2, and the last (if of order >= 16)
+    dc_handle hV = 0, hVl = 0, hY = 0;   // inverse tiles 0..T-2 and T-1; solve scratch
+    if (inv) TRY(regs.mat(&hY, base + o_y, n, r, r, DC_F64, 0));
     if (inv && T > 1) TRY(regs.mat(&hV, base + o_v, (T - 1) * tile, tile, tile, DC_F64, A));
     if (inv && nlast >= 16)
       TRY(regs.mat(&hVl, base + o_v + (size_t)(T - 1) * tile * tile * 8, nlast, nlast, tile,
@@ -236,17 +239,22 @@ extern "C" int dc_posv_ir(dc_runtime *rt, dc_handle A, dc_handle B, dc_handle X,
     for (int64_t i = 0; i < T; ++i)
       for (int64_t j = 0; j < T; ++j) L[i * T + j] = i == j ? D[i] : Wt[i * T + j];
     auto solve_into = [&](dc_handle V) -> int {
-      // V (n x r) is solved in place with the mixed factor
-      std::vector<dc_handle> vt(T * ((r + tile - 1) / tile));
-      TRY(dc_matrix_partition(rt, V, tile, vt.data()));
+      // V (n x r) is solved in place with the mixed factor (through the
+      // scratch Y when the inverses are there)
       const int64_t tc = (r + tile - 1) / tile;
-      std::vector<dc_handle> rows(T);
-      int e = 0;
+      std::vector<dc_handle> vt(T * tc), yt(T * tc);
+      TRY(dc_matrix_partition(rt, V, tile, vt.data()));
+      int e = inv ? dc_matrix_partition(rt, hY, tile, yt.data()) : 0;
+      std::vector<dc_handle> rows(T), yrows(T);
       for (int64_t j = 0; j < tc && !e; ++j) {
-        for (int64_t i = 0; i < T; ++i) rows[i] = vt[i * tc + j];
-        e = dcx_submit_potrs_tiles(rt, L, T, rows, inv ? &Vall : nullptr);
+        for (int64_t i = 0; i < T; ++i) {
+          rows[i] = vt[i * tc + j];
+          yrows[i] = yt[i * tc + j];
+        }
+        e = dcx_submit_potrs_tiles(rt, L, T, rows, inv ? &Vall : nullptr, inv ? &yrows : nullptr);
       }
       if (!e) e = dc_wait_all(rt);
+      if (inv) dc_matrix_unpartition(rt, hY);
       dc_matrix_unpartition(rt, V);
       return e;
     };

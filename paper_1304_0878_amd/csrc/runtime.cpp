@@ -355,8 +355,8 @@ static const KindSig kSig[DC_NUM_KINDS] = {
     {2, {DC_R, DC_W}},                  // TRTRI
     {3, {DC_R, DC_R, DC_RW}},           // TRSM_INV
     {4, {DC_R, DC_R, DC_RW, DC_W}},     // TRSM_INV_CAST
-    {3, {DC_R, DC_R, DC_RW}},           // TRSM_L_INV
-    {3, {DC_R, DC_R, DC_RW}},           // TRSM_LT_INV
+    {4, {DC_R, DC_R, DC_R, DC_W}},      // TRSM_L_INV
+    {4, {DC_R, DC_R, DC_R, DC_W}},      // TRSM_LT_INV
 };
 
 static int units_for(const TaskDesc &d) {
@@ -367,7 +367,8 @@ static int units_for(const TaskDesc &d) {
     case K_TRSM: case K_TRSM_CAST: case K_TRTRI: case K_TRSM_INV: case K_TRSM_INV_CAST:
       return std::max(1, cdiv(d.m, trsm_rows(d.n)));
     case K_GEMM_RHS_N: case K_GEMM_RHS_T: return std::max(1, cdiv(d.m, RHS_ROWS));
-    case K_TRSM_L_INV: case K_TRSM_LT_INV: return std::max(1, cdiv(d.n, 16));
+    case K_TRSM_L_INV: case K_TRSM_LT_INV:
+      return std::max(1, cdiv(d.m, SOLVE_INV_ROWS) * cdiv(d.n, 16));
     case K_CAST: case K_RESID: case K_AXPY:
       return std::max(1, cdiv(d.m, ROW_UNIT));
     case K_SCAL: return std::max(1, cdiv(d.m, 4096));
@@ -471,15 +472,17 @@ static int make_desc(dc_runtime *rt, dc_kind kind, const std::vector<Handle *> &
       break;
     }
     case DC_TRSM_L_INV: case DC_TRSM_LT_INV: {
-      Handle *L = H[0], *W = H[1], *B = H[2];
-      if (!f64(L) || !f64(W) || !f64(B)) return -EINVAL;
+      Handle *L = H[0], *W = H[1], *S = H[2], *D = H[3];
+      if (!f64(L) || !f64(W) || !f64(S) || !f64(D)) return -EINVAL;
       if (L->rows != L->cols || W->rows != L->rows || W->cols != L->rows ||
-          B->rows != L->rows || L->rows < 16 || L->rows > MAX_TILE)
+          S->rows != L->rows || D->rows != S->rows || D->cols != S->cols || L->rows < 16 ||
+          L->rows > MAX_TILE || S->ptr == D->ptr)
         return -EINVAL;
-      d.m = (int)L->rows; d.n = (int)B->cols;
+      d.m = (int)L->rows; d.n = (int)S->cols;
       d.a = W->ptr; d.lda = W->ld; d.ta = W->dtype;
       d.b = L->ptr; d.ldb = L->ld; d.tb = L->dtype;
-      d.c = B->ptr; d.ldc = B->ld; d.tc = B->dtype;
+      d.c = S->ptr; d.ldc = S->ld; d.tc = S->dtype;
+      d.d = D->ptr; d.ldd = D->ld;
       break;
     }
     case DC_GEMM_RHS_N: case DC_GEMM_RHS_T: {

@@ -33,7 +33,8 @@
 #include "runtime_internal.h"
 
 int dcx_submit_potrs_tiles(dc_runtime *rt, const std::vector<dc_handle> &L, int64_t T,
-                           const std::vector<dc_handle> &B, const std::vector<dc_handle> *V);
+                           const std::vector<dc_handle> &B, const std::vector<dc_handle> *V,
+                           const std::vector<dc_handle> *Y);
 
 namespace {
 
@@ -113,11 +114,12 @@ struct Slot {
   // workspace layout (device pointers)
   double *diag = nullptr, *r = nullptr;
   void *w = nullptr, *s = nullptr, *v = nullptr;
+  double *y = nullptr;                   // solve scratch (n x r)
   double *hx = nullptr, *hd = nullptr;   // pinned host copies of x and d
   size_t host_cap = 0;
   std::vector<dc_handle> regs;
-  dc_handle hA = 0, hB = 0, hX = 0, hR = 0, hW = 0, hS = 0, hV = 0, hVl = 0;
-  std::vector<dc_handle> D, Wt, Vall;
+  dc_handle hA = 0, hB = 0, hX = 0, hR = 0, hW = 0, hS = 0, hV = 0, hVl = 0, hY = 0;
+  std::vector<dc_handle> D, Wt, Vall, Yt;
   int64_t T = 0;
   int it = 0;
   std::vector<double> prev;
@@ -143,13 +145,22 @@ struct dc_server {
 
 namespace {
 
+// Panel solves and the diagonal steps of the solves go through the inverses
+// of the diagonal factors when every diagonal tile has order >= 16.
+bool uses_inverses(const dc_server_config &c, int64_t n) {
+  return c.tile >= 16 && n - (n - 1) / c.tile * c.tile >= 16;
+}
+
 size_t footprint(const dc_server_config &c, int64_t n, int64_t r, dc_dtype prec) {
   const int64_t T = (n + c.tile - 1) / c.tile;
   size_t b = al256((size_t)T * c.tile * c.tile * 8);            // FP64 diagonal tiles
   b += al256((size_t)n * n * (prec == DC_F64 ? 8 : 4));         // off-diagonal tiles
   if (prec == DC_BF16) b += al256((size_t)n * n * 2);           // BF16 copies
   b += al256((size_t)n * r * 8);                                // residual / correction
-  if (c.tile >= 16) b += al256((size_t)T * c.tile * c.tile * 8);   // inverses
+  if (uses_inverses(c, n)) {
+    b += al256((size_t)T * c.tile * c.tile * 8);                 // inverses
+    b += al256((size_t)n * r * 8);                              // solve scratch
+  }
   return b;
 }
 
@@ -169,6 +180,8 @@ void release_slot(dc_server *srv, Slot &s) {
   s.Wt.clear();
   if (!s.Vall.empty() && s.hV) dc_matrix_unpartition(s.rt, s.hV);
   s.Vall.clear();
+  if (!s.Yt.empty()) dc_matrix_unpartition(s.rt, s.hY);
+  s.Yt.clear();
   for (auto it = s.regs.rbegin(); it != s.regs.rend(); ++it) dc_unregister(s.rt, *it);
   s.regs.clear();
   s.D.clear();
@@ -208,11 +221,15 @@ int solve_into(Slot &s, dc_handle V) {
   const int64_t tc = (s.req.r + tile - 1) / tile;
   std::vector<dc_handle> vt(s.T * tc);
   TRY(dc_matrix_partition(s.rt, V, tile, vt.data()));
-  std::vector<dc_handle> rows(s.T);
+  std::vector<dc_handle> rows(s.T), yrows(s.T);
   int e = 0;
   for (int64_t j = 0; j < tc && !e; ++j) {
-    for (int64_t i = 0; i < s.T; ++i) rows[i] = vt[i * tc + j];
-    e = dcx_submit_potrs_tiles(s.rt, L, s.T, rows, s.v ? &s.Vall : nullptr);
+    for (int64_t i = 0; i < s.T; ++i) {
+      rows[i] = vt[i * tc + j];
+      if (s.v) yrows[i] = s.Yt[i * tc + j];
+    }
+    e = dcx_submit_potrs_tiles(s.rt, L, s.T, rows, s.v ? &s.Vall : nullptr,
+                               s.v ? &yrows : nullptr);
   }
   // the row blocks stay registered until the graph ran; unpartitioning waits
   // for them, so it happens when the step is collected
@@ -242,7 +259,11 @@ int start(dc_server *srv, Slot &s, const Request &q, size_t off, size_t bytes) {
   s.r = (double *)(base + o); o += al256((size_t)n * r * 8);
   // inverses of the diagonal factors: panel solves and the diagonal steps of
   // the solves become MFMA products
-  s.v = c.tile >= 16 ? base + o : nullptr;
+  s.v = s.y = nullptr;
+  if (uses_inverses(c, n)) {
+    s.v = base + o; o += al256((size_t)s.T * tile * tile * 8);
+    s.y = (double *)(base + o);
+  }
   if (s.host_cap < (size_t)n * r) {
     if (s.hx) hipHostFree(s.hx);
     if (s.hd) hipHostFree(s.hd);
@@ -263,9 +284,11 @@ int start(dc_server *srv, Slot &s, const Request &q, size_t off, size_t bytes) {
   s.hV = s.hVl = 0;
   const int64_t last = n - (s.T - 1) * tile;
   if (s.v && s.T > 1) TRY(reg(s, &s.hV, s.v, (s.T - 1) * tile, tile, tile, DC_F64, s.hA));
-  if (s.v && last >= 16)
+  if (s.v)
     TRY(reg(s, &s.hVl, (char *)s.v + (size_t)(s.T - 1) * tile * tile * 8, last, last, tile, DC_F64,
             s.hA));
+  s.hY = 0;
+  if (s.y) TRY(reg(s, &s.hY, s.y, n, r, r, DC_F64, 0));
   s.D.assign(s.T, 0);
   for (int64_t k = 0; k < s.T; ++k) {
     const int64_t nb = std::min(tile, n - k * tile);
@@ -350,6 +373,8 @@ int step(dc_server *srv, Slot &s) {
         s.Vall.assign(s.T, 0);
         if (s.hV) TRY(dc_matrix_partition(s.rt, s.hV, c.tile, s.Vall.data()));
         s.Vall[s.T - 1] = s.hVl;
+        s.Yt.assign(s.T * ((r + c.tile - 1) / c.tile), 0);
+        TRY(dc_matrix_partition(s.rt, s.hY, c.tile, s.Yt.data()));
       }
       // x0 = solve(b); then r = b - A x0 and d = solve(r).  Each flush
       // releases the handles it used, so partitions can change between the

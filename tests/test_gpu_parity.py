@@ -191,21 +191,25 @@ def test_trsm_inv_falls_back_to_substitution(dc, rt, torch_dev, m, nb):
 
 
 def _with_inverse(dc, rt, torch_dev, l, b, kind):
-    """TRTRI then one task of `kind` (L, W, B) on B; returns B."""
+    """TRTRI, then one out-of-place task of `kind` (L, W, S = b, D); returns D
+    and checks that S was only read."""
     torch, dev = torch_dev
     nb = l.shape[0]
     tl, tb = _gpu(torch_dev, l), _gpu(torch_dev, b)
     tw = torch.zeros((nb, nb), dtype=torch.float64, device=dev)
-    hl, hw, hb = rt.register_tensor(tl), rt.register_tensor(tw), rt.register_tensor(tb)
-    rt.dc_task_submit(dc.DC_TRTRI, [hl, hw], [dc.DC_R, dc.DC_W])
-    rt.dc_task_submit(kind, [hl, hw, hb], [dc.DC_R, dc.DC_R, dc.DC_RW])
+    td = torch.full(b.shape, float("nan"), dtype=torch.float64, device=dev)
+    hs = [rt.register_tensor(t) for t in (tl, tw, tb, td)]
+    rt.dc_task_submit(dc.DC_TRTRI, hs[:2], [dc.DC_R, dc.DC_W])
+    rt.dc_task_submit(kind, hs, [dc.DC_R, dc.DC_R, dc.DC_R, dc.DC_W])
     rt.dc_wait_all()
-    for h in (hl, hw, hb):
+    for h in hs:
         rt.dc_unregister(h)
-    return tb.cpu().numpy()
+    assert np.array_equal(tb.cpu().numpy(), b)
+    return td.cpu().numpy()
 
 
-@pytest.mark.parametrize("nb,r", [(512, 1), (512, 16), (100, 3), (16, 1), (256, 20), (37, 40)])
+@pytest.mark.parametrize("nb,r", [(512, 1), (512, 16), (100, 3), (16, 1), (256, 20), (37, 40),
+                                  (200, 70)])
 def test_solve_steps_through_inverse(dc, rt, torch_dev, nb, r):
     l = np.linalg.cholesky(inputs.spd_uniform(nb, 2 * nb + r))
     assert _amp(l) <= 1024

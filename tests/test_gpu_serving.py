@@ -97,11 +97,12 @@ def test_server_small_pool_admits_one_at_a_time(dc, torch_dev):
     tile = 128
     t = (n + tile - 1) // tile
     # workspaces: FP64 diagonal tiles + off-diagonal tiles + residual + the
-    # inverses of the diagonal factors; the pool must hold one FP64
-    # workspace (a restart must always fit) but not two FP32 ones
-    inv = t * tile * tile * 8
+    # inverses of the diagonal factors + the solve scratch; the pool must
+    # hold one FP64 workspace (a restart must always fit) but not two FP32
+    # ones
+    inv = t * tile * tile * 8 + n * 3 * 8
     fp32 = t * tile * tile * 8 + n * n * 4 + n * 3 * 8 + inv
-    fp64 = t * tile * tile * 8 + n * n * 8 + n * 3 * 8 + inv + 4 * 256
+    fp64 = t * tile * tile * 8 + n * n * 8 + n * 3 * 8 + inv + 5 * 256
     assert fp64 < 2 * fp32
     pool = (fp64 + 2 * fp32) // 2
     res, xs = _serve(dc, torch_dev, systems, slots=4, tile=tile, pool_bytes=pool)
