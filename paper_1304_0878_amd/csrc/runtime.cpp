@@ -760,6 +760,10 @@ static size_t lds_for(const TaskDesc &d) {
   }
 }
 
+// Fewest CUs the panel kernel gets next to the GEMM kernels (measured at
+// n = 32768, tile 512: 16 beats 0, 40, 64 and 96).
+constexpr int PANEL_MIN_CUS = 16;
+
 // Rough duration (ns) of a task on one CU, for balancing levels.
 static double cost_ns(const TaskDesc &d) {
   const double m = d.m, n = d.n, k = d.k;
@@ -1001,9 +1005,14 @@ extern "C" int dc_flush(dc_runtime *rt) {
       dcx_level_occupancy(llds[L], &per_cu);
       pcus = cus;
       if (hasg) {
-        // CUs shared in proportion to the estimated work of the two kernels
+        // CUs shared in proportion to the estimated work of the two kernels,
+        // but at least PANEL_MIN_CUS (or one per panel item): a level often
+        // holds a POTRF and the 32 units of a TRTRI or TRSM_INV on the
+        // critical path next to hundreds of GEMMs, and the proportional
+        // share alone would queue them on two or three CUs
         const double share = pcost[L] / std::max(1.0, pcost[L] + gcost[L]);
-        pcus = std::min(std::max(1, (int)std::ceil(share * cus)), cus - 1);
+        const int floor_cus = (int)std::min<int64_t>(pcount[L], PANEL_MIN_CUS);
+        pcus = std::min(std::max({1, (int)std::ceil(share * cus), floor_cus}), cus - 1);
       }
       pworkers = (int)std::min<int64_t>(pcount[L], (int64_t)pcus * std::max(1, per_cu));
     }
