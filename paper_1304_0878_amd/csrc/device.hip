@@ -1230,7 +1230,14 @@ __device__ __forceinline__ uint64_t uniform_u64(uint64_t v) {
   return ((uint64_t)hi << 32) | lo;
 }
 
-__global__ void __launch_bounds__(NT, 1) dc_level_kernel(LevelArgs A) {
+// Two instances: the full one (every kind; the factorisation's and the
+// solves' units need up to about 500 registers per lane, so one workgroup
+// per CU) and a light one for levels whose units are all residual or
+// elementwise work (RESID, CAST, AXPY, SCAL), which keeps to 128 registers
+// so four workgroups share a CU and hide the memory latency these units are
+// bound by.
+template <bool LIGHT>
+__global__ void __launch_bounds__(NT, LIGHT ? 4 : 1) dc_level_kernel(LevelArgs A) {
   extern __shared__ double lds[];
   __shared__ uint64_t s_idx;
   __shared__ int s_skip;
@@ -1255,19 +1262,13 @@ __global__ void __launch_bounds__(NT, 1) dc_level_kernel(LevelArgs A) {
     const int kind = __builtin_amdgcn_readfirstlane(d.kind);
     if (!skip) {
       switch (kind) {
-        case K_TRSM: case K_TRSM_CAST: run_trsm(d, u, lds); break;
-        case K_TRTRI: trsm_core<true>(d, u, lds, (const gdouble *)d.a, d.lda); break;
-        case K_TRSM_INV: case K_TRSM_INV_CAST: run_trsm_inv(d, u, lds); break;
-        case K_TRSM_L_INV: run_trsm_l_inv<true>(d, u, lds); break;
-        case K_TRSM_LT_INV: run_trsm_l_inv<false>(d, u, lds); break;
-        case K_POTRF: {
-          const int bad = run_potrf(d, lds);
-          if (bad && tid == 0 && d.matrix >= 0) {
-            A.info[d.matrix] = d.row0 + bad;
-            A.failed[d.matrix] = 1;
-          }
-          break;
-        }
+        case K_SCAL: run_scal(d, u); break;
+        case K_CAST: run_cast(d, u); break;
+        case K_RESID: run_resid(d, u, lds); break;
+        case K_AXPY: run_axpy(d, u); break;
+        default: break;
+      }
+      if (!LIGHT) switch (kind) {
         case K_TRSM_L:
           if (d.ta == T_F32) run_trsm_l<float>(d, lds); else run_trsm_l<double>(d, lds);
           break;
@@ -1280,10 +1281,19 @@ __global__ void __launch_bounds__(NT, 1) dc_level_kernel(LevelArgs A) {
         case K_GEMM_RHS_T:
           if (d.ta == T_F32) run_gemm_rhs_t<float>(d, u, lds); else run_gemm_rhs_t<double>(d, u, lds);
           break;
-        case K_SCAL: run_scal(d, u); break;
-        case K_CAST: run_cast(d, u); break;
-        case K_RESID: run_resid(d, u, lds); break;
-        case K_AXPY: run_axpy(d, u); break;
+        case K_TRSM_L_INV: run_trsm_l_inv<true>(d, u, lds); break;
+        case K_TRSM_LT_INV: run_trsm_l_inv<false>(d, u, lds); break;
+        case K_TRSM: case K_TRSM_CAST: run_trsm(d, u, lds); break;
+        case K_TRTRI: trsm_core<true>(d, u, lds, (const gdouble *)d.a, d.lda); break;
+        case K_TRSM_INV: case K_TRSM_INV_CAST: run_trsm_inv(d, u, lds); break;
+        case K_POTRF: {
+          const int bad = run_potrf(d, lds);
+          if (bad && tid == 0 && d.matrix >= 0) {
+            A.info[d.matrix] = d.row0 + bad;
+            A.failed[d.matrix] = 1;
+          }
+          break;
+        }
         default: break;
       }
     }
@@ -1314,15 +1324,26 @@ extern "C" int dc_selftest(void *dev_ptr, int64_t n, void *stream) {
   return hipStreamSynchronize((hipStream_t)stream) == hipSuccess ? 0 : -5;
 }
 
-int dcx_launch_level(const LevelArgs &args, int workers, size_t lds_bytes, void *stream) {
-  hipLaunchKernelGGL(dc_level_kernel, dim3(workers), dim3(NT), lds_bytes, (hipStream_t)stream, args);
+int dcx_launch_level(const LevelArgs &args, int workers, size_t lds_bytes, bool light,
+                     void *stream) {
+  if (light)
+    hipLaunchKernelGGL(dc_level_kernel<true>, dim3(workers), dim3(NT), lds_bytes,
+                       (hipStream_t)stream, args);
+  else
+    hipLaunchKernelGGL(dc_level_kernel<false>, dim3(workers), dim3(NT), lds_bytes,
+                       (hipStream_t)stream, args);
   return (int)hipGetLastError();
 }
 
 int dcx_level_setup(void) {
-  return (int)hipFuncSetAttribute((const void *)dc_level_kernel,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  LDS_DOUBLES * (int)sizeof(double));
+  hipError_t e = hipFuncSetAttribute((const void *)dc_level_kernel<false>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     LDS_DOUBLES * (int)sizeof(double));
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void *)dc_level_kernel<true>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize,
+                            LDS_DOUBLES * (int)sizeof(double));
+  return (int)e;
 }
 
 extern "C" int dc_executor_limits(int device, int64_t *out, int n) {
@@ -1332,9 +1353,9 @@ extern "C" int dc_executor_limits(int device, int64_t *out, int n) {
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, device) != hipSuccess) return -5;
   hipFuncAttributes fa;
-  if (hipFuncGetAttributes(&fa, (const void *)dc_level_kernel) != hipSuccess) return -5;
+  if (hipFuncGetAttributes(&fa, (const void *)dc_level_kernel<false>) != hipSuccess) return -5;
   int nb = 0;
-  hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, dc_level_kernel, NT,
+  hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, dc_level_kernel<false>, NT,
                                                LDS_DOUBLES * sizeof(double));
   out[0] = (int64_t)prop.sharedMemPerBlock;
   out[1] = (int64_t)prop.maxSharedMemoryPerMultiProcessor;
@@ -1346,9 +1367,12 @@ extern "C" int dc_executor_limits(int device, int64_t *out, int n) {
   return 0;
 }
 
-int dcx_level_occupancy(size_t lds_bytes, int *blocks_per_cu) {
+int dcx_level_occupancy(size_t lds_bytes, bool light, int *blocks_per_cu) {
   int nb = 0;
-  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, dc_level_kernel, NT, lds_bytes);
+  hipError_t e = light ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, dc_level_kernel<true>,
+                                                                      NT, lds_bytes)
+                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, dc_level_kernel<false>,
+                                                                      NT, lds_bytes);
   *blocks_per_cu = nb;
   return (int)e;
 }

@@ -92,8 +92,9 @@ struct LevelArgs {
 }  // namespace dcx
 
 // Launches one level on `stream` (a hipStream_t); returns a hipError_t value.
+// light: the instance for levels of solve, residual and elementwise units.
 extern "C++" int dcx_launch_level(const dcx::LevelArgs &args, int workers, size_t lds_bytes,
-                                  void *stream);
+                                  bool light, void *stream);
 // Allows the level kernel its largest dynamic LDS size.
 extern "C++" int dcx_level_setup(void);
 // Launches the GEMM/SYRK kernel for inputs of dtype ta (T_F64 or T_F32) of
@@ -104,4 +105,4 @@ extern "C++" int dcx_launch_gemm_lowp(const dcx::LevelArgs &args, int workers, v
 // Allows the GEMM/SYRK kernels their dynamic LDS sizes.
 extern "C++" int dcx_gemm_setup(void);
 // Workgroups per CU the level kernel keeps resident with lds_bytes of LDS.
-extern "C++" int dcx_level_occupancy(size_t lds_bytes, int *blocks_per_cu);
+extern "C++" int dcx_level_occupancy(size_t lds_bytes, bool light, int *blocks_per_cu);

@@ -949,6 +949,12 @@ extern "C" int dc_flush(dc_runtime *rt) {
     filll[L] = fill32[L] + g32count[L];
   }
   std::vector<size_t> llds(nl, 16);
+  // levels whose panel units are all residual or elementwise work run the
+  // light instance of the panel kernel
+  auto light_kind = [](int kind) {
+    return kind == K_SCAL || kind == K_CAST || kind == K_RESID || kind == K_AXPY;
+  };
+  std::vector<char> llight(nl, 1);
   for (int64_t i = 0; i < nt; ++i) {
     const int64_t t = order[i];
     const Task &k = rt->tasks[t];
@@ -956,6 +962,7 @@ extern "C" int dc_flush(dc_runtime *rt) {
     const int L = level[t];
     const bool g = is_gemm(k.desc);
     if (!g) llds[L] = std::max(llds[L], lds_for(k.desc));
+    if (!g && !light_kind(k.desc.kind)) llight[L] = 0;
     int64_t &fp = !g ? fillp[L]
                   : !is_g64(k.desc) ? filll[L]
                   : k.desc.ta == T_F64 ? fillg[L] : fill32[L];
@@ -1002,7 +1009,7 @@ extern "C" int dc_flush(dc_runtime *rt) {
     int pworkers = 0, pcus = 0;
     if (hasp) {
       int per_cu = 1;
-      dcx_level_occupancy(llds[L], &per_cu);
+      dcx_level_occupancy(llds[L], llight[L] != 0, &per_cu);
       pcus = cus;
       if (hasg) {
         // CUs shared in proportion to the estimated work of the two kernels,
@@ -1039,7 +1046,7 @@ extern "C" int dc_flush(dc_runtime *rt) {
       a.count = pcount[L];
       a.counter = (unsigned long long *)(db + o_cnt) + 4 * L;
       const size_t tb = timing ? tev(pstream) : 0;
-      int le = dcx_launch_level(a, pworkers, llds[L], pstream);
+      int le = dcx_launch_level(a, pworkers, llds[L], llight[L] != 0, pstream);
       if (le != 0) { fail_hip((hipError_t)le, "level launch"); drop(); return -EIO; }
       if (timing) {
         const size_t te = tev(pstream);
