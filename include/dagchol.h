@@ -367,6 +367,10 @@ typedef struct {
   int upd;             /* dc_dtype of the trailing updates */
   double tol;          /* refinement stopping threshold */
   int maxit;           /* refinement steps before giving up */
+  int64_t whole_max;   /* requests of order <= whole_max (<= 512) are
+                          factored as a single tile, larger ones with
+                          `tile`; default 512, 0: every request uses
+                          `tile` */
 } dc_server_config;
 
 typedef struct {

@@ -145,20 +145,28 @@ struct dc_server {
 
 namespace {
 
+// Tile size of a request: orders up to whole_max are factored as one tile
+// (one POTRF task and one diagonal step per sweep): fewer levels per
+// request, but one workgroup carries the whole factorisation.
+int64_t tile_for(const dc_server_config &c, int64_t n) {
+  return (n <= c.whole_max && n >= 1) ? n : c.tile;
+}
+
 // Panel solves and the diagonal steps of the solves go through the inverses
 // of the diagonal factors when every diagonal tile has order >= 16.
-bool uses_inverses(const dc_server_config &c, int64_t n) {
-  return c.tile >= 16 && n - (n - 1) / c.tile * c.tile >= 16;
+bool uses_inverses(int64_t tile, int64_t n) {
+  return tile >= 16 && n - (n - 1) / tile * tile >= 16;
 }
 
 size_t footprint(const dc_server_config &c, int64_t n, int64_t r, dc_dtype prec) {
-  const int64_t T = (n + c.tile - 1) / c.tile;
-  size_t b = al256((size_t)T * c.tile * c.tile * 8);            // FP64 diagonal tiles
+  const int64_t tile = tile_for(c, n);
+  const int64_t T = (n + tile - 1) / tile;
+  size_t b = al256((size_t)T * tile * tile * 8);                // FP64 diagonal tiles
   b += al256((size_t)n * n * (prec == DC_F64 ? 8 : 4));         // off-diagonal tiles
   if (prec == DC_BF16) b += al256((size_t)n * n * 2);           // BF16 copies
   b += al256((size_t)n * r * 8);                                // residual / correction
-  if (uses_inverses(c, n)) {
-    b += al256((size_t)T * c.tile * c.tile * 8);                 // inverses
+  if (uses_inverses(tile, n)) {
+    b += al256((size_t)T * tile * tile * 8);                    // inverses
     b += al256((size_t)n * r * 8);                              // solve scratch
   }
   return b;
@@ -248,7 +256,7 @@ int start(dc_server *srv, Slot &s, const Request &q, size_t off, size_t bytes) {
   s.converged = false;
   s.prev.assign(q.r, INFINITY);
   const dc_server_config &c = srv->cfg;
-  const int64_t n = q.n, r = q.r, tile = c.tile;
+  const int64_t n = q.n, r = q.r, tile = tile_for(c, n);
   s.T = (n + tile - 1) / tile;
   char *base = (char *)srv->pool_ptr + off;
   size_t o = 0;
@@ -260,7 +268,7 @@ int start(dc_server *srv, Slot &s, const Request &q, size_t off, size_t bytes) {
   // inverses of the diagonal factors: panel solves and the diagonal steps of
   // the solves become MFMA products
   s.v = s.y = nullptr;
-  if (uses_inverses(c, n)) {
+  if (uses_inverses(tile, n)) {
     s.v = base + o; o += al256((size_t)s.T * tile * tile * 8);
     s.y = (double *)(base + o);
   }
@@ -368,13 +376,14 @@ int step(dc_server *srv, Slot &s) {
         return 0;
       }
       s.Wt.assign(s.T * s.T, 0);
-      TRY(dc_matrix_partition(s.rt, s.hW, c.tile, s.Wt.data()));
+      const int64_t tile = tile_for(c, n);
+      TRY(dc_matrix_partition(s.rt, s.hW, tile, s.Wt.data()));
       if (s.v) {
         s.Vall.assign(s.T, 0);
-        if (s.hV) TRY(dc_matrix_partition(s.rt, s.hV, c.tile, s.Vall.data()));
+        if (s.hV) TRY(dc_matrix_partition(s.rt, s.hV, tile, s.Vall.data()));
         s.Vall[s.T - 1] = s.hVl;
-        s.Yt.assign(s.T * ((r + c.tile - 1) / c.tile), 0);
-        TRY(dc_matrix_partition(s.rt, s.hY, c.tile, s.Yt.data()));
+        s.Yt.assign(s.T * ((r + tile - 1) / tile), 0);
+        TRY(dc_matrix_partition(s.rt, s.hY, tile, s.Yt.data()));
       }
       // x0 = solve(b); then r = b - A x0 and d = solve(r).  Each flush
       // releases the handles it used, so partitions can change between the
@@ -462,6 +471,7 @@ extern "C" void dc_server_config_default(dc_server_config *c) {
   c->slots = 4;
   c->pool_bytes = (size_t)64 << 30;
   c->tile = 256;
+  c->whole_max = dcx::MAX_TILE;
   c->upd = DC_F32;
   c->tol = 1e-12;
   c->maxit = 30;
@@ -473,6 +483,7 @@ extern "C" int dc_server_create(dc_server **out, const dc_server_config *cfg) {
   dc_server_config c;
   if (cfg) c = *cfg; else dc_server_config_default(&c);
   if (c.slots < 1 || c.slots > 64 || c.tile < 1 || c.tile > dcx::MAX_TILE || c.pool_bytes == 0 ||
+      c.whole_max < 0 || c.whole_max > dcx::MAX_TILE ||
       !(c.tol > 0) || c.maxit < 0 || (c.upd != DC_F64 && c.upd != DC_F32 && c.upd != DC_BF16))
     return -EINVAL;
   dc_server *srv = new (std::nothrow) dc_server();

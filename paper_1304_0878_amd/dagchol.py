@@ -64,7 +64,7 @@ class dc_kernel_stats(ctypes.Structure):
 class dc_server_config(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int), ("slots", ctypes.c_int), ("pool_bytes", ctypes.c_size_t),
                 ("tile", ctypes.c_int64), ("upd", ctypes.c_int), ("tol", ctypes.c_double),
-                ("maxit", ctypes.c_int)]
+                ("maxit", ctypes.c_int), ("whole_max", ctypes.c_int64)]
 
 
 class dc_request(ctypes.Structure):
@@ -416,11 +416,13 @@ class Server:
     submit() are kept alive here until their request completes."""
 
     def __init__(self, device=0, slots=4, pool_bytes=None, tile=256, upd=DC_F32, tol=1e-12,
-                 maxit=30):
+                 maxit=30, whole_max=None):
         cfg = dc_server_config()
         _lib.dc_server_config_default(ctypes.byref(cfg))
         cfg.device, cfg.slots, cfg.tile, cfg.upd = device, slots, tile, upd
         cfg.tol, cfg.maxit = tol, maxit
+        if whole_max is not None:
+            cfg.whole_max = whole_max
         if pool_bytes is not None:
             cfg.pool_bytes = pool_bytes
         p = _P()

@@ -91,6 +91,22 @@ def test_server_alone_equals_in_mix(dc, torch_dev):
         assert np.array_equal(x1[0], xs[i])
 
 
+def test_server_whole_tile_requests(dc, torch_dev):
+    # orders up to whole_max (512 unless set) are factored as one tile, the
+    # others with the configured tile; both kinds share the pool and the
+    # launches
+    systems = _systems(8, 7, nmin=16, nmax=700)
+    res, xs = _serve(dc, torch_dev, systems, slots=4, tile=128, whole_max=512)
+    for (a, b), r, x in zip(systems, res, xs):
+        assert r["status"] == 0 and r["converged"] == 1 and r["info"] == 0, r
+        xref = mixed.reference_solution(a, b, 128)
+        assert np.abs(x - xref).max() / np.abs(xref).max() <= 1e-10, r
+    small = [i for i, (a, _) in enumerate(systems) if a.shape[0] <= 512]
+    assert small
+    _, x1 = _serve(dc, torch_dev, [systems[small[0]]], slots=1, tile=128, whole_max=512)
+    assert np.array_equal(x1[0], xs[small[0]])
+
+
 def test_server_small_pool_admits_one_at_a_time(dc, torch_dev):
     systems = _systems(5, 5, nmin=500, nmax=500)
     n = 500
@@ -105,7 +121,7 @@ def test_server_small_pool_admits_one_at_a_time(dc, torch_dev):
     fp64 = t * tile * tile * 8 + n * n * 8 + n * 3 * 8 + inv + 5 * 256
     assert fp64 < 2 * fp32
     pool = (fp64 + 2 * fp32) // 2
-    res, xs = _serve(dc, torch_dev, systems, slots=4, tile=tile, pool_bytes=pool)
+    res, xs = _serve(dc, torch_dev, systems, slots=4, tile=tile, whole_max=0, pool_bytes=pool)
     res = sorted(res, key=lambda r: r["admitted"])
     for prev, cur in zip(res, res[1:]):
         assert cur["admitted"] >= prev["completed"] - 1e-9
