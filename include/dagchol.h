@@ -316,9 +316,12 @@ int dc_potrs(dc_runtime *rt, dc_handle L, dc_handle B, int64_t tile);
  * DC_F64.  x0 = solve(b); then r = b - A x (FP64 storage, computed as a
  * compensated dot product per row, as accurate as twice-FP64 arithmetic
  * rounded once), d = solve(r), x += d, until ||d||_inf <= tol ||x||_inf for
- * every column (converged; that last d is still added), stagnation
- * (||d_i|| > 0.5 ||d_{i-1}|| in some column; d_i is not added) or maxit
- * steps.  If the factor breaks down or refinement does not converge,
+ * every column (converged; that last d is still added), or, from the second
+ * correction on, until the error left after adding d_i, estimated from the
+ * contraction ratio as ||d_i||^2 / (||d_{i-1}|| - ||d_i||), is <= tol ||x||_inf
+ * for every column (converged, d_i added; this saves the solve that would
+ * only confirm it), stagnation (||d_i|| > 0.5 ||d_{i-1}|| in some column;
+ * d_i is not added) or maxit steps.  If the factor breaks down or refinement does not converge,
  * the next wider precision is used (BF16 -> FP32 -> FP64).  B and X are
  * n x r FP64; X receives the solution. */
 typedef struct {
@@ -351,9 +354,10 @@ int dc_potrf_batched(dc_runtime *rt, int64_t count, const dc_handle *A, const dc
  * admitted in arrival order as soon as one of `slots` slots and enough of the
  * server's device memory pool are free; each admitted request runs on its own
  * runtime and streams, so the work of requests in different slots overlaps on
- * the GPU.  Per request: copy of A into the pool, factorisation (FP64
+ * the GPU.  Per request (A is read in place and must stay alive until the
+ * request completes): factorisation into a workspace in the pool (FP64
  * diagonal tiles, off-diagonal updates at precision `upd`), solve and
- * FP64-residual refinement to ||d||_inf <= tol ||x||_inf per column; a
+ * FP64-residual refinement with the stopping tests of dc_posv_ir; a
  * breakdown or failed refinement restarts the request with the next wider
  * update precision (BF16 -> FP32 -> FP64).
  * The server object is driven by one host thread. */

@@ -293,18 +293,19 @@ extern "C" int dc_posv_ir(dc_runtime *rt, dc_handle A, dc_handle B, dc_handle X,
       }
       colmax(hd, dn);
       colmax(hx, xn);
-      bool all_small = true, any_grow = false;
+      bool all_small = true, any_grow = false, left_small = it > 0;
       last = 0.0;
       for (int64_t c = 0; c < r; ++c) {
         if (!(dn[c] <= tol * xn[c])) all_small = false;
         if (it > 0 && dn[c] > 0.5 * prev[c]) any_grow = true;
+        if (it > 0 && !(dcx_remaining_error(dn[c], prev[c]) <= tol * xn[c])) left_small = false;
         last = std::max(last, xn[c] > 0 ? dn[c] / xn[c] : dn[c]);
       }
       if (any_grow && !all_small) break;   // stagnation: d not added
       e = submit(rt, DC_AXPY, {hR, X}, {DC_R, DC_RW}, 0);
       if (!e) e = dc_wait_all(rt);
       if (e) break;
-      if (all_small) { converged = true; break; }
+      if (all_small || left_small) { converged = true; break; }
       if (++it >= maxit) break;
       prev = dn;
     }

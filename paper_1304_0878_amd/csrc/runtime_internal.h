@@ -16,6 +16,16 @@ enum HandleKind { HK_VECTOR = 0, HK_MATRIX = 1 };
 // returns -EIO.
 int dcx_fail_hip(hipError_t e, const char *what);
 
+// Refinement: error left after adding a correction of norm dn whose
+// predecessor had norm prev, with the corrections taken to contract
+// geometrically at the observed ratio rho = dn / prev:
+// rho dn / (1 - rho) = dn^2 / (prev - dn) (the estimate of extra-precise
+// iterative refinement, Demmel et al., ACM TOMS 2006).  Only called when
+// dn <= prev / 2 (no stagnation), so prev - dn > 0 wherever dn > 0.
+inline double dcx_remaining_error(double dn, double prev) {
+  return dn > 0 ? dn * dn / (prev - dn) : 0.0;
+}
+
 struct Handle {
   int kind = HK_MATRIX;
   void *ptr = nullptr;

@@ -14,7 +14,8 @@
 // Per request (A is only read): factor A (FP64 diagonal tiles;
 // off-diagonal tiles FP32 with FP32 or BF16 updates, or all FP64), solve,
 // then refine with the FP64 residual r = b - A x until ||d|| <= tol ||x||
-// (per column) or stagnation; a breakdown or a failed refinement restarts the
+// or the contraction estimate of the error left is (per column), or
+// stagnation; a breakdown or a failed refinement restarts the
 // request with the next wider update precision (BF16 -> FP32 -> FP64).  Every step only submits tasks through
 // dc_task_submit and flushes.
 #include <errno.h>
@@ -415,11 +416,13 @@ int step(dc_server *srv, Slot &s) {
           dn[k] = std::max(dn[k], std::fabs(s.hd[i * r + k]));
           xn[k] = std::max(xn[k], std::fabs(s.hx[i * r + k]));
         }
-      bool small = true, grow = false;
+      bool small = true, grow = false, left_small = s.it > 0;
       s.last = 0.0;
       for (int64_t k = 0; k < r; ++k) {
         if (!(dn[k] <= c.tol * xn[k])) small = false;
         if (s.it > 0 && dn[k] > 0.5 * s.prev[k]) grow = true;
+        if (s.it > 0 && !(dcx_remaining_error(dn[k], s.prev[k]) <= c.tol * xn[k]))
+          left_small = false;
         s.last = std::max(s.last, xn[k] > 0 ? dn[k] / xn[k] : dn[k]);
       }
       if (grow && !small) {
@@ -428,11 +431,11 @@ int step(dc_server *srv, Slot &s) {
         return 0;
       }
       TRY(submit(s.rt, DC_AXPY, {s.hR, s.hX}, {DC_R, DC_RW}, 0));
-      if (small || s.it + 1 >= c.maxit) {
+      if (small || left_small || s.it + 1 >= c.maxit) {
         TRY(launch(s));
         s.phase = P_FINISH;
-        s.converged = small;
-        if (!small) s.it += 1;
+        s.converged = small || left_small;
+        if (!s.converged) s.it += 1;
         return 0;
       }
       s.prev = dn;

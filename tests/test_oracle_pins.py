@@ -527,6 +527,33 @@ def test_refine_mixed_reaches_reference():
     assert np.abs(r).max() <= 4 * U * (np.abs(a).sum(1).max() * np.abs(xref).max())
 
 
+def test_refine_stops_on_predicted_contraction():
+    """Closed form: with the factor c L of c^2 A (L the FP64 factor of A),
+    refinement contracts by exactly rho = 1 - 1/c^2 per step, so
+    ||d_k|| = rho^(k+1) ||x*|| / c^2.  With c = 1 + 2^-9 and tol = 1e-11
+    the correction test alone is met first at k = 4 (rho^5 = 9e-13); the
+    contraction estimate ||d_k||^2 / (||d_{k-1}|| - ||d_k||), which here
+    equals the sum of the corrections still to come, is met at k = 3
+    (2.3e-10 at k = 2), so the refinement ends after 3 steps with x within
+    the estimate of x*."""
+    n = 64
+    a = inputs.spd_cond(n, 41, 10.0)
+    bm = inputs.rhs(n, 2, 42)
+    l = np.tril(core.potrf_tiled(a, 16)[0])
+    c = 1.0 + 2.0 ** -9
+    rho = 1.0 - 1.0 / (c * c)
+    x, it, status = mixed.refine(a, bm, c * l, 16, tol=1e-11)
+    assert status == "converged" and it == 3
+    xref = mixed.reference_solution(a, bm, 16)
+    err = np.abs(x - xref).max(axis=0) / np.abs(xref).max(axis=0)
+    assert np.all(err <= 2 * rho ** 5 / (1 - rho)) and np.all(err > 1e-14)
+    # rho = 0.4 (c^2 = 5/3), tol = 5.1e-4: the estimate rho^(k+2) ||x*|| is
+    # first met at k = 7 (rho^8 = 6.6e-4 at k = 6); without its 1 / (1 - rho)
+    # it would be met at k = 6 (0.6 rho^8 = 3.9e-4)
+    x, it, status = mixed.refine(a, bm, np.sqrt(5.0 / 3.0) * l, 16, tol=5.1e-4)
+    assert status == "converged" and it == 7
+
+
 def test_delta_for_cond_hits_target():
     gram = inputs.normal_gram(300, 5)
     for kappa in (1e2, 1e4, 1e6):
