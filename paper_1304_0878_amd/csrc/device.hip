@@ -1236,8 +1236,13 @@ __device__ __forceinline__ uint64_t uniform_u64(uint64_t v) {
 // elementwise work (RESID, CAST, AXPY, SCAL), which keeps to 128 registers
 // so four workgroups share a CU and hide the memory latency these units are
 // bound by.
-template <bool LIGHT>
-__global__ void __launch_bounds__(NT, LIGHT ? 4 : 1) dc_level_kernel(LevelArgs A) {
+// Three instances, each compiled with only the units it runs so that its
+// register allocation is its own: LI_FULL runs every kind (one workgroup
+// per CU), LI_LIGHT the residual and elementwise units, LI_RHS the
+// right-hand-side updates of the solves (both four workgroups per CU: their
+// units stream from memory).
+template <int MODE>
+__global__ void __launch_bounds__(NT, MODE == LI_FULL ? 1 : 4) dc_level_kernel(LevelArgs A) {
   extern __shared__ double lds[];
   __shared__ uint64_t s_idx;
   __shared__ int s_skip;
@@ -1261,25 +1266,28 @@ __global__ void __launch_bounds__(NT, LIGHT ? 4 : 1) dc_level_kernel(LevelArgs A
     const int skip = __builtin_amdgcn_readfirstlane(s_skip);
     const int kind = __builtin_amdgcn_readfirstlane(d.kind);
     if (!skip) {
-      switch (kind) {
+      if (MODE != LI_RHS) switch (kind) {
         case K_SCAL: run_scal(d, u); break;
         case K_CAST: run_cast(d, u); break;
         case K_RESID: run_resid(d, u, lds); break;
         case K_AXPY: run_axpy(d, u); break;
         default: break;
       }
-      if (!LIGHT) switch (kind) {
-        case K_TRSM_L:
-          if (d.ta == T_F32) run_trsm_l<float>(d, lds); else run_trsm_l<double>(d, lds);
-          break;
-        case K_TRSM_LT:
-          if (d.ta == T_F32) run_trsm_lt<float>(d, lds); else run_trsm_lt<double>(d, lds);
-          break;
+      if (MODE != LI_LIGHT) switch (kind) {
         case K_GEMM_RHS_N:
           if (d.ta == T_F32) run_gemm_rhs_n<float>(d, u, lds); else run_gemm_rhs_n<double>(d, u, lds);
           break;
         case K_GEMM_RHS_T:
           if (d.ta == T_F32) run_gemm_rhs_t<float>(d, u, lds); else run_gemm_rhs_t<double>(d, u, lds);
+          break;
+        default: break;
+      }
+      if (MODE == LI_FULL) switch (kind) {
+        case K_TRSM_L:
+          if (d.ta == T_F32) run_trsm_l<float>(d, lds); else run_trsm_l<double>(d, lds);
+          break;
+        case K_TRSM_LT:
+          if (d.ta == T_F32) run_trsm_lt<float>(d, lds); else run_trsm_lt<double>(d, lds);
           break;
         case K_TRSM_L_INV: run_trsm_l_inv<true>(d, u, lds); break;
         case K_TRSM_LT_INV: run_trsm_l_inv<false>(d, u, lds); break;
@@ -1324,25 +1332,28 @@ extern "C" int dc_selftest(void *dev_ptr, int64_t n, void *stream) {
   return hipStreamSynchronize((hipStream_t)stream) == hipSuccess ? 0 : -5;
 }
 
-int dcx_launch_level(const LevelArgs &args, int workers, size_t lds_bytes, bool light,
+int dcx_launch_level(const LevelArgs &args, int workers, size_t lds_bytes, int inst,
                      void *stream) {
-  if (light)
-    hipLaunchKernelGGL(dc_level_kernel<true>, dim3(workers), dim3(NT), lds_bytes,
+  if (inst == LI_LIGHT)
+    hipLaunchKernelGGL(dc_level_kernel<LI_LIGHT>, dim3(workers), dim3(NT), lds_bytes,
+                       (hipStream_t)stream, args);
+  else if (inst == LI_RHS)
+    hipLaunchKernelGGL(dc_level_kernel<LI_RHS>, dim3(workers), dim3(NT), lds_bytes,
                        (hipStream_t)stream, args);
   else
-    hipLaunchKernelGGL(dc_level_kernel<false>, dim3(workers), dim3(NT), lds_bytes,
+    hipLaunchKernelGGL(dc_level_kernel<LI_FULL>, dim3(workers), dim3(NT), lds_bytes,
                        (hipStream_t)stream, args);
   return (int)hipGetLastError();
 }
 
 int dcx_level_setup(void) {
-  hipError_t e = hipFuncSetAttribute((const void *)dc_level_kernel<false>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     LDS_DOUBLES * (int)sizeof(double));
-  if (e == hipSuccess)
-    e = hipFuncSetAttribute((const void *)dc_level_kernel<true>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize,
-                            LDS_DOUBLES * (int)sizeof(double));
+  hipError_t e = hipSuccess;
+  for (const void *f : {(const void *)dc_level_kernel<LI_FULL>,
+                        (const void *)dc_level_kernel<LI_LIGHT>,
+                        (const void *)dc_level_kernel<LI_RHS>})
+    if (e == hipSuccess)
+      e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              LDS_DOUBLES * (int)sizeof(double));
   return (int)e;
 }
 
@@ -1353,9 +1364,9 @@ extern "C" int dc_executor_limits(int device, int64_t *out, int n) {
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, device) != hipSuccess) return -5;
   hipFuncAttributes fa;
-  if (hipFuncGetAttributes(&fa, (const void *)dc_level_kernel<false>) != hipSuccess) return -5;
+  if (hipFuncGetAttributes(&fa, (const void *)dc_level_kernel<LI_FULL>) != hipSuccess) return -5;
   int nb = 0;
-  hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, dc_level_kernel<false>, NT,
+  hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, dc_level_kernel<LI_FULL>, NT,
                                                LDS_DOUBLES * sizeof(double));
   out[0] = (int64_t)prop.sharedMemPerBlock;
   out[1] = (int64_t)prop.maxSharedMemoryPerMultiProcessor;
@@ -1367,12 +1378,15 @@ extern "C" int dc_executor_limits(int device, int64_t *out, int n) {
   return 0;
 }
 
-int dcx_level_occupancy(size_t lds_bytes, bool light, int *blocks_per_cu) {
+int dcx_level_occupancy(size_t lds_bytes, int inst, int *blocks_per_cu) {
   int nb = 0;
-  hipError_t e = light ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, dc_level_kernel<true>,
-                                                                      NT, lds_bytes)
-                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, dc_level_kernel<false>,
-                                                                      NT, lds_bytes);
+  hipError_t e =
+      inst == LI_LIGHT ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                             &nb, dc_level_kernel<LI_LIGHT>, NT, lds_bytes)
+      : inst == LI_RHS ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                             &nb, dc_level_kernel<LI_RHS>, NT, lds_bytes)
+                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                             &nb, dc_level_kernel<LI_FULL>, NT, lds_bytes);
   *blocks_per_cu = nb;
   return (int)e;
 }

@@ -56,6 +56,8 @@ __host__ __device__ constexpr int solve_lds_doubles(int nb) {
 constexpr int SOLVE_INV_ROWS = 64;
 // Rows of a right-hand-side update unit (GEMM_RHS_N, GEMM_RHS_T) and its LDS.
 constexpr int RHS_ROWS = 16;
+// instances of the level kernel
+constexpr int LI_FULL = 0, LI_LIGHT = 1, LI_RHS = 2;
 constexpr int RHS_LDS_DOUBLES = 16 * 16 * 8;
 constexpr int PANEL_LDS_DOUBLES = 2 * TRSM_ROWS * (MAX_TILE + 2) + PANEL * (PANEL + 1);
 
@@ -92,9 +94,11 @@ struct LevelArgs {
 }  // namespace dcx
 
 // Launches one level on `stream` (a hipStream_t); returns a hipError_t value.
-// light: the instance for levels of solve, residual and elementwise units.
+// inst: the instance of the level kernel (dcx::LI_FULL for any units,
+// LI_LIGHT for residual and elementwise units only, LI_RHS for solve
+// right-hand-side updates only).
 extern "C++" int dcx_launch_level(const dcx::LevelArgs &args, int workers, size_t lds_bytes,
-                                  bool light, void *stream);
+                                  int inst, void *stream);
 // Allows the level kernel its largest dynamic LDS size.
 extern "C++" int dcx_level_setup(void);
 // Launches the GEMM/SYRK kernel for inputs of dtype ta (T_F64 or T_F32) of
@@ -105,4 +109,4 @@ extern "C++" int dcx_launch_gemm_lowp(const dcx::LevelArgs &args, int workers, v
 // Allows the GEMM/SYRK kernels their dynamic LDS sizes.
 extern "C++" int dcx_gemm_setup(void);
 // Workgroups per CU the level kernel keeps resident with lds_bytes of LDS.
-extern "C++" int dcx_level_occupancy(size_t lds_bytes, bool light, int *blocks_per_cu);
+extern "C++" int dcx_level_occupancy(size_t lds_bytes, int inst, int *blocks_per_cu);

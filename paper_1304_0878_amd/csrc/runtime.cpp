@@ -950,11 +950,14 @@ extern "C" int dc_flush(dc_runtime *rt) {
   }
   std::vector<size_t> llds(nl, 16);
   // levels whose panel units are all residual or elementwise work run the
-  // light instance of the panel kernel
+  // light instance of the panel kernel, levels of solve right-hand-side
+  // updates only the RHS instance (both four workgroups per CU: these units
+  // stream from memory); any other level the full instance
   auto light_kind = [](int kind) {
     return kind == K_SCAL || kind == K_CAST || kind == K_RESID || kind == K_AXPY;
   };
-  std::vector<char> llight(nl, 1);
+  auto rhs_kind = [](int kind) { return kind == K_GEMM_RHS_N || kind == K_GEMM_RHS_T; };
+  std::vector<char> llight(nl, 1), lrhs(nl, 1);
   for (int64_t i = 0; i < nt; ++i) {
     const int64_t t = order[i];
     const Task &k = rt->tasks[t];
@@ -963,6 +966,7 @@ extern "C" int dc_flush(dc_runtime *rt) {
     const bool g = is_gemm(k.desc);
     if (!g) llds[L] = std::max(llds[L], lds_for(k.desc));
     if (!g && !light_kind(k.desc.kind)) llight[L] = 0;
+    if (!g && !rhs_kind(k.desc.kind)) lrhs[L] = 0;
     int64_t &fp = !g ? fillp[L]
                   : !is_g64(k.desc) ? filll[L]
                   : k.desc.ta == T_F64 ? fillg[L] : fill32[L];
@@ -997,6 +1001,7 @@ extern "C" int dc_flush(dc_runtime *rt) {
     if (hipEventRecord(rt->tevents[ntev], st) != hipSuccess) return SIZE_MAX;
     return ntev++;
   };
+  auto linst = [&](int64_t L) { return lrhs[L] ? LI_RHS : llight[L] ? LI_LIGHT : LI_FULL; };
   for (int64_t L = 0; L < nl; ++L) {
     LevelArgs a;
     a.desc = (const TaskDesc *)(db + o_desc);
@@ -1009,7 +1014,7 @@ extern "C" int dc_flush(dc_runtime *rt) {
     int pworkers = 0, pcus = 0;
     if (hasp) {
       int per_cu = 1;
-      dcx_level_occupancy(llds[L], llight[L] != 0, &per_cu);
+      dcx_level_occupancy(llds[L], linst(L), &per_cu);
       pcus = cus;
       if (hasg) {
         // CUs shared in proportion to the estimated work of the two kernels,
@@ -1046,7 +1051,7 @@ extern "C" int dc_flush(dc_runtime *rt) {
       a.count = pcount[L];
       a.counter = (unsigned long long *)(db + o_cnt) + 4 * L;
       const size_t tb = timing ? tev(pstream) : 0;
-      int le = dcx_launch_level(a, pworkers, llds[L], llight[L] != 0, pstream);
+      int le = dcx_launch_level(a, pworkers, llds[L], linst(L), pstream);
       if (le != 0) { fail_hip((hipError_t)le, "level launch"); drop(); return -EIO; }
       if (timing) {
         const size_t te = tev(pstream);
