@@ -361,32 +361,33 @@ __device__ __forceinline__ void trsm_inv_product(const TaskDesc &d, int unit, do
 }
 
 // Diagonal step of a solve through W = L^{-1}, out of place: D <- W S
-// (forward) or D <- W^T S (backward), S and D nb x r.  A unit is 64 rows of
-// D (one 16-row block per wave) by 16 columns, so a step spreads over
-// nb/64 x r/16 workgroups that stream disjoint rows (forward) or columns
-// (backward) of W.  The 16 columns of S are staged as the 16 rows of
-// X = S^T over the K range the unit's rows need (k <= i forward, k >= i
-// backward); out[c][i] = sum_k X[c][k] Wop[i][k], Wop = W or W^T, with
-// 16x16x4 FP64 MFMA.
+// (forward) or D <- W^T S (backward), S and D nb x r.  A unit is one 16-row
+// block of D by 16 columns, so a step spreads over nb/16 x r/16 workgroups
+// that stream disjoint rows (forward) or columns (backward) of W.  The 16
+// columns of S are staged as the 16 rows of X = S^T over the K range the
+// block needs (k <= i forward, k >= i backward); out[c][i] =
+// sum_k X[c][k] Wop[i][k], Wop = W or W^T, with 16x16x4 FP64 MFMA.  The
+// four waves take every fourth 16-column chunk of that range and their
+// partial sums are added in LDS in wave order (a fixed order: the result
+// does not depend on timing).
 template <bool FULL, bool FWD>
 __device__ __forceinline__ void solve_inv_product(const TaskDesc &d, int unit, double *lds) {
   const int nb = d.m, r = d.n;
   const int nb16 = (nb + 15) / 16;
   const int ncc = (r + 15) / 16;
-  const int rb = unit / ncc, c0 = 16 * (unit - rb * ncc);
+  const int b = unit / ncc, c0 = 16 * (unit - b * ncc);   // b < nb16 by the unit count
   const int rc = min(16, r - c0);
   const int XS = panel_stride(nb);
   const gdouble *W = (const gdouble *)d.a;
   const int64_t ldw = d.lda;
   const gdouble *Sm = (const gdouble *)d.c;
   gdouble *Dm = (gdouble *)d.d;
-  // chunks the unit's four blocks need
-  static_assert(SOLVE_INV_ROWS == 4 * 16, "one 16-row block per wave");
-  const int b0 = 4 * rb;
-  const int kc_lo = FWD ? 0 : b0;
-  const int kc_hi = FWD ? min(nb16, b0 + 4) : nb16;   // exclusive
+  static_assert(SOLVE_INV_ROWS == 16, "one 16-row block per unit");
+  const int kc_lo = FWD ? 0 : b;
+  const int kc_hi = FWD ? b + 1 : nb16;   // exclusive
   const int k_lo = 16 * kc_lo, k_hi = min(nb, 16 * kc_hi);
-  double *Xs = lds;
+  double *Xs = lds;                      // 16 x XS
+  double *red = lds + 16 * XS;           // partial sums of waves 1..3
   for (int idx = threadIdx.x; idx < 16 * (k_hi - k_lo); idx += NT) {
     const int k = k_lo + (idx >> 4), c = idx & 15;
     Xs[c * XS + k] = c < rc ? Sm[(int64_t)k * d.ldc + c0 + c] : 0.0;
@@ -394,13 +395,10 @@ __device__ __forceinline__ void solve_inv_product(const TaskDesc &d, int unit, d
   __syncthreads();
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int l16 = lane & 15, kq = lane >> 4;
-  const int b = b0 + w;                      // this wave's block of rows
-  const int col = 16 * b + l16;              // output row i of this lane
+  const int col = 16 * b + l16;          // output row i of this lane
   typedef double dvec4 __attribute__((ext_vector_type(4)));
   dvec4 acc = dvec4{0.0, 0.0, 0.0, 0.0};
-  auto active = [&](int kc) { return b < nb16 && (FWD ? kc <= b : kc >= b); };
   auto wload = [&](int kc, double (&v)[4]) {
-    if (!active(kc)) return;
     const int k = 16 * kc + 4 * kq;
     if (!FWD) {
 #pragma unroll
@@ -422,7 +420,6 @@ __device__ __forceinline__ void solve_inv_product(const TaskDesc &d, int unit, d
     }
   };
   auto chunk = [&](int kc, const double (&v)[4]) {
-    if (!active(kc)) return;
     const int k = 16 * kc + 4 * kq;
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
@@ -430,25 +427,32 @@ __device__ __forceinline__ void solve_inv_product(const TaskDesc &d, int unit, d
       acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, v[s], acc, 0, 0, 0);
     }
   };
-  // up to four chunks of loads in flight ahead of the multiplications
+  // wave w takes chunks kc_lo + w, + 4, + 8, ...; four of them in flight
   double v0[4] = {0, 0, 0, 0}, v1[4] = {0, 0, 0, 0}, v2[4] = {0, 0, 0, 0}, v3[4] = {0, 0, 0, 0};
-  for (int kc = kc_lo; kc < kc_hi; kc += 4) {
+  for (int kc = kc_lo + w; kc < kc_hi; kc += 16) {
     wload(kc, v0);
-    if (kc + 1 < kc_hi) wload(kc + 1, v1);
-    if (kc + 2 < kc_hi) wload(kc + 2, v2);
-    if (kc + 3 < kc_hi) wload(kc + 3, v3);
+    if (kc + 4 < kc_hi) wload(kc + 4, v1);
+    if (kc + 8 < kc_hi) wload(kc + 8, v2);
+    if (kc + 12 < kc_hi) wload(kc + 12, v3);
     chunk(kc, v0);
-    if (kc + 1 < kc_hi) chunk(kc + 1, v1);
-    if (kc + 2 < kc_hi) chunk(kc + 2, v2);
-    if (kc + 3 < kc_hi) chunk(kc + 3, v3);
+    if (kc + 4 < kc_hi) chunk(kc + 4, v1);
+    if (kc + 8 < kc_hi) chunk(kc + 8, v2);
+    if (kc + 12 < kc_hi) chunk(kc + 12, v3);
   }
+  if (w > 0) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) red[((w - 1) * 4 + e) * 64 + lane] = acc[e];
+  }
+  __syncthreads();
   // result element e of lane l: row (right-hand side) l/16 + 4e, column
   // (row i of D) l%16 of the block
-  if (b < nb16 && col < nb) {
+  if (w == 0 && col < nb) {
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
+      double v = acc[e];
+      for (int q = 0; q < 3; ++q) v += red[(q * 4 + e) * 64 + lane];
       const int c = kq + 4 * e;
-      if (c < rc) Dm[(int64_t)col * d.ldd + c0 + c] = acc[e];
+      if (c < rc) Dm[(int64_t)col * d.ldd + c0 + c] = v;
     }
   }
 }

@@ -53,7 +53,7 @@ __host__ __device__ constexpr int solve_lds_doubles(int nb) {
 }
 // Rows of D one unit of an out-of-place diagonal solve step (TRSM_L_INV,
 // TRSM_LT_INV) produces.
-constexpr int SOLVE_INV_ROWS = 64;
+constexpr int SOLVE_INV_ROWS = 16;
 // Rows of a right-hand-side update unit (GEMM_RHS_N, GEMM_RHS_T) and its LDS.
 constexpr int RHS_ROWS = 16;
 // instances of the level kernel

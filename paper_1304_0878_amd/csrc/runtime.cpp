@@ -753,7 +753,9 @@ static size_t lds_for(const TaskDesc &d) {
     case K_POTRF: return (size_t)potrf_lds_doubles(d.m) * 8;
     case K_TRSM_L: case K_TRSM_LT: return (size_t)solve_lds_doubles(d.m) * 8;
     case K_TRSM_L_INV: case K_TRSM_LT_INV:
-      return (size_t)std::max(solve_lds_doubles(d.m), TRSM_ROWS * panel_stride(d.m)) * 8;
+      // X staging (16 rows of the panel stride) and the partial sums of
+      // three waves (3 x 4 x 64)
+      return (size_t)std::max(solve_lds_doubles(d.m), 16 * panel_stride(d.m) + 3 * 4 * 64) * 8;
     case K_GEMM_RHS_N: case K_GEMM_RHS_T: return (size_t)RHS_LDS_DOUBLES * 8;
     case K_RESID: return (size_t)(2 * 64 * 8 + 4 * 64 * 8) * 8;
     default: return 16;
