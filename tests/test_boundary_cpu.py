@@ -173,3 +173,22 @@ def test_ragged_partition_shapes(dc):
 def test_strerror(dc):
     assert "unregistered" in dc.dc_strerror(-2)
     assert dc.dc_strerror(0) == "success"
+
+
+def test_server_config_validation(dc):
+    """dc_server_create checks its configuration before touching a device:
+    defaults, then each out-of-range field rejected with -EINVAL."""
+    lib = dc._lib
+    cfg = dc.dc_server_config()
+    lib.dc_server_config_default(ctypes.byref(cfg))
+    assert (cfg.slots, cfg.tile, cfg.whole_max, cfg.upd, cfg.maxit) == (4, 256, 512, dc.DC_F32, 30)
+    assert cfg.tol == 1e-12 and cfg.pool_bytes == 64 << 30
+    for field, bad in (("whole_max", 513), ("whole_max", -1), ("tile", 0), ("tile", 513),
+                       ("slots", 0), ("slots", 65), ("tol", 0.0), ("maxit", -1), ("upd", 7),
+                       ("pool_bytes", 0)):
+        c = dc.dc_server_config()
+        lib.dc_server_config_default(ctypes.byref(c))
+        setattr(c, field, bad)
+        out = ctypes.c_void_p()
+        assert lib.dc_server_create(ctypes.byref(out), ctypes.byref(c)) == -22, (field, bad)
+        assert not out.value
