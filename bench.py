@@ -35,17 +35,22 @@ PROFILE = os.path.join(ROOT, "profiles", "dc_gemm_kernel_fp64_n32768.md")
 def stored_traffic(n, tile):
     """HBM bytes per launch of the GEMM kernel from the committed rocprofv3
     counter summary, or None when it does not apply: another workload, or a
-    kernel source that changed since the counters were taken (SHA-256)."""
+    change since the counters were taken (SHA-256) in the kernel source or in
+    the sources that decide what one launch holds (the executor's levels and
+    the factorisation's task graph)."""
     import hashlib
     if (n, tile) != (32768, 512) or not os.path.exists(PROFILE):
         return None
     for line in open(PROFILE):
         if line.startswith("traffic: "):
             rec = json.loads(line[len("traffic: "):])
-            src = os.path.join(ROOT, rec["source"])
-            with open(src, "rb") as f:
-                if hashlib.sha256(f.read()).hexdigest() != rec["source_sha256"]:
-                    return None
+            shas = rec.get("source_sha256s")
+            if not isinstance(shas, dict) or not shas:
+                return None
+            for rel, sha in shas.items():
+                with open(os.path.join(ROOT, rel), "rb") as f:
+                    if hashlib.sha256(f.read()).hexdigest() != sha:
+                        return None
             return rec["bytes_per_launch"]
     return None
 

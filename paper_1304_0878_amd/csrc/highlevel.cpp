@@ -74,18 +74,25 @@ void dcx_discard_pending(dc_runtime *rt) {
 // Right-looking tiled factorisation on partitioned tiles (submission only).
 // Priorities (Section 5.3's hints): the diagonal factor, the panel TRSMs and
 // the updates of the next panel column come first.  With inverse workspaces
-// W (one per diagonal tile but the last), the panel solves of column k are
-// TRTRI(k) followed by TRSM_INV(i, k).
+// W (one per diagonal tile but the last), the panel solves of column k are a
+// substitution TRSM for tile (k+1, k), and TRTRI(k) followed by
+// TRSM_INV(i, k) for i >= k + 2.
 int dcx_submit_potrf_tiles(dc_runtime *rt, const std::vector<dc_handle> &A, int64_t T,
                            const std::vector<dc_handle> *W) {
   auto at = [&](int64_t i, int64_t j) { return A[i * T + j]; };
   for (int64_t k = 0; k < T; ++k) {
     TRY(submit1(rt, DC_POTRF, at(k, k), DC_RW, 0));
     if (W && k + 1 < T) {
-      TRY(submit2(rt, DC_TRTRI, at(k, k), DC_R, (*W)[k], DC_W, 0));
-      for (int64_t i = k + 1; i < T; ++i)
-        TRY(submit3(rt, DC_TRSM_INV, at(k, k), DC_R, (*W)[k], DC_R, at(i, k), DC_RW,
-                    i == k + 1 ? 0 : 1));
+      // The tile below the diagonal leads to the next POTRF: it is solved by
+      // substitution straight from L_kk, so the inversion of L_kk, which
+      // only the tiles further down need, runs beside it instead of ahead
+      // of it on the critical path.
+      TRY(submit2(rt, DC_TRSM, at(k, k), DC_R, at(k + 1, k), DC_RW, 0));
+      if (k + 2 < T) {
+        TRY(submit2(rt, DC_TRTRI, at(k, k), DC_R, (*W)[k], DC_W, 0));
+        for (int64_t i = k + 2; i < T; ++i)
+          TRY(submit3(rt, DC_TRSM_INV, at(k, k), DC_R, (*W)[k], DC_R, at(i, k), DC_RW, 1));
+      }
     } else {
       for (int64_t i = k + 1; i < T; ++i)
         TRY(submit2(rt, DC_TRSM, at(k, k), DC_R, at(i, k), DC_RW, i == k + 1 ? 0 : 1));

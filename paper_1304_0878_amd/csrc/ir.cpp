@@ -92,7 +92,9 @@ double now_ms() {
 // precision upd into the workspace: D[k] FP64 diagonal tiles, W (FP32) and S
 // (BF16) off-diagonal tile handles.  For upd == FP64 the tiles W are FP64.
 // With V (T - 1 FP64 tiles), the panel solves of column k are TRTRI(D[k])
-// into V[k] and TRSM_INV (TRSM_INV_CAST for BF16) instead of TRSM.
+// into V[k] and TRSM_INV (TRSM_INV_CAST for BF16) instead of TRSM, except
+// for tile (k+1, k): it leads to the next POTRF and is solved by
+// substitution, so TRTRI runs beside it rather than ahead of it.
 int submit_mixed_factor(dc_runtime *rt, int64_t T, int64_t tile, const std::vector<dc_handle> &At,
                         const std::vector<dc_handle> &D, const std::vector<dc_handle> &W,
                         const std::vector<dc_handle> &S, dc_dtype upd,
@@ -113,10 +115,11 @@ int submit_mixed_factor(dc_runtime *rt, int64_t T, int64_t tile, const std::vect
     if (inv) TRY(submit(rt, DC_TRTRI, {D[k], (*V)[k]}, {DC_R, DC_W}, 0));
     for (int64_t i = k + 1; i < T; ++i) {
       const int pr = i == k + 1 ? 0 : 1;
-      if (inv && bf)
+      const bool inv_i = inv && i != k + 1;
+      if (inv_i && bf)
         TRY(submit(rt, DC_TRSM_INV_CAST, {D[k], (*V)[k], w(i, k), s(i, k)},
                    {DC_R, DC_R, DC_RW, DC_W}, pr));
-      else if (inv)
+      else if (inv_i)
         TRY(submit(rt, DC_TRSM_INV, {D[k], (*V)[k], w(i, k)}, {DC_R, DC_R, DC_RW}, pr));
       else if (bf)
         TRY(submit(rt, DC_TRSM_CAST, {D[k], w(i, k), s(i, k)}, {DC_R, DC_RW, DC_W}, pr));

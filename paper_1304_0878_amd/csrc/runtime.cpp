@@ -1026,9 +1026,13 @@ extern "C" int dc_flush(dc_runtime *rt) {
         // share alone would queue them on two or three CUs
         const double share = pcost[L] / std::max(1.0, pcost[L] + gcost[L]);
         const int floor_cus = (int)std::min<int64_t>(pcount[L], PANEL_MIN_CUS);
-        pcus = std::min(std::max({1, (int)std::ceil(share * cus), floor_cus}), cus - 1);
+        // with a single CU both kernels get it (they are independent within
+        // a level, so running one after the other is fine)
+        pcus = std::min(std::max({1, (int)std::ceil(share * cus), floor_cus}),
+                        std::max(1, cus - 1));
       }
-      pworkers = (int)std::min<int64_t>(pcount[L], (int64_t)pcus * std::max(1, per_cu));
+      pworkers = (int)std::max<int64_t>(
+          1, std::min<int64_t>(pcount[L], (int64_t)pcus * std::max(1, per_cu)));
     }
     // CUs left to the GEMM kernels.  Both take one workgroup per CU (a
     // whole CU's LDS or registers), so launching gcus of them leaves pcus

@@ -326,7 +326,9 @@ int start(dc_server *srv, Slot &s, const Request &q, size_t off, size_t bytes) {
     if (inv && !e) e = submit(s.rt, DC_TRTRI, {s.D[k], V[k]}, {DC_R, DC_W}, 0);
     for (int64_t i = k + 1; i < s.T && !e; ++i) {
       const int pr = i == k + 1 ? 0 : 1;
-      if (inv)
+      // tile (k+1, k) leads to the next POTRF: substitution, so that TRTRI
+      // is not ahead of it on the critical path
+      if (inv && i != k + 1)
         e = bf ? submit(s.rt, DC_TRSM_INV_CAST, {s.D[k], V[k], w(i, k), sh(i, k)},
                         {DC_R, DC_R, DC_RW, DC_W}, pr)
                : submit(s.rt, DC_TRSM_INV, {s.D[k], V[k], w(i, k)}, {DC_R, DC_R, DC_RW}, pr);
