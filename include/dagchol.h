@@ -297,9 +297,10 @@ int dc_kernel_stats_get(dc_runtime *rt, dc_kernel_stats *out);
  * dc_potrf: tiled right-looking Cholesky of the lower triangle of A in
  * place, in FP64: for k, POTRF(k); TRSM(i,k) for i>k; SYRK(i,k) and
  * GEMM(i,j,k) for k<j<i.  Result: dc_get_info(A).  With tile >= 16 the
- * panel solves of column k are TRTRI(k) into a workspace W_k followed by
- * TRSM_INV(i,k) for i>k (same result up to rounding; ill-conditioned
- * diagonal tiles fall back to substitution, see DC_TRSM_INV).  The runtime
+ * panel solves of column k are TRSM(k+1,k) by substitution (it leads to the
+ * next POTRF) and, for i >= k+2, TRTRI(k) into a workspace W_k followed by
+ * TRSM_INV(i,k) (same result up to rounding; ill-conditioned diagonal tiles
+ * fall back to substitution, see DC_TRSM_INV).  The runtime
  * keeps the workspace, (tiles - 1) * tile^2 doubles, until dc_shutdown;
  * -ENOMEM if it cannot be allocated. */
 int dc_potrf(dc_runtime *rt, dc_handle A, int64_t tile);
