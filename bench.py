@@ -298,6 +298,7 @@ def main():
     ap.add_argument("--batch-count", type=int, default=10000)
     ap.add_argument("--serve-requests", type=int, default=200)
     ap.add_argument("--serve-nmax", type=int, default=16384)
+
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:

@@ -12,8 +12,16 @@
  * 5.1 the partitioning of a registered matrix into sub-matrix handles, the
  * idiom of tiled Cholesky; Section 5.3 task priorities as scheduling hints.
  *
- * The tasks run on the GPU inside one persistent executor kernel that pops
- * ready work from device-side queues as dependency counters reach zero.
+ * The tasks run on the GPU.  The executor (DC_EXEC_LEVELS) splits each
+ * flushed graph into levels on the host (every task's predecessors in
+ * earlier levels) and runs each level as one launch of the panel kernel
+ * (POTRF, the triangular solves, elementwise tasks) next to the GEMM/SYRK
+ * kernels, on two streams; within a launch, workgroups take work items from
+ * an atomic counter, urgent priority lanes first (Section 5.3's hints).
+ * A device-side ready-queue executor (DC_EXEC_QUEUE: persistent kernels
+ * whose workgroups pop ready items and decrement their successors'
+ * dependency counters) is built but disabled: dc_init rejects it with
+ * -ENOSYS (its first run on the GPU did not complete).
  *
  * Conventions for every entry point
  * ---------------------------------
@@ -27,7 +35,7 @@
  *                  referenced by pending tasks;
  *      -ENOMEM     host or device memory exhausted, or a capacity exceeded;
  *      -ENODEV     execution requested from a host-only runtime;
- *      -ETIMEDOUT  the executor's watchdog fired;
+ *      -ENOSYS     a disabled feature was requested;
  *      -EIO        a HIP runtime call failed.
  *    The library never aborts the process (unlike the paper's generated
  *    code, which calls abort on these errors).
@@ -129,23 +137,32 @@ typedef enum {
   DC_NUM_KINDS = 18
 } dc_kind;
 
+/* Executors (dc_config.executor). */
+typedef enum { DC_EXEC_LEVELS = 0, DC_EXEC_QUEUE = 1 } dc_executor;
+
 typedef struct {
   int device;            /* HIP device ordinal; -1: host-only runtime that
                             builds and inspects graphs but cannot execute */
   void *stream;          /* hipStream_t to issue work on; NULL: a stream the
                             runtime creates */
-  int workers;           /* persistent workgroups; 0: one per CU times the
-                            kernel's occupancy */
-  int64_t watchdog_ms;   /* executor gives up after this long without
-                            progress; 0: 60000 */
+  int workers;           /* CUs the executor's kernels may use together;
+                            0: every CU of the device */
+  int64_t watchdog_ms;   /* reserved for DC_EXEC_QUEUE (a worker that waits
+                            this long while no task completes would stop the
+                            graph with -ETIMEDOUT); the level executor never
+                            waits on the device; 0: 60000 */
   int trace;             /* nonzero: record a per-task trace at every wait */
+  int executor;          /* dc_executor; 0 (DC_EXEC_LEVELS) by default;
+                            DC_EXEC_QUEUE is rejected (-ENOSYS) */
 } dc_config;
 
-/* Fills cfg with defaults (device 0, own stream, automatic workers). */
+/* Fills cfg with defaults (device 0, own stream, every CU, level executor,
+ * 60 s watchdog). */
 void dc_config_default(dc_config *cfg);
 
-/* Creates a runtime.  Errors: -EINVAL (null pointer), -EIO (HIP failure,
- * e.g. no such device), -ENOMEM. */
+/* Creates a runtime.  Errors: -EINVAL (null pointer, unknown executor),
+ * -ENOSYS (DC_EXEC_QUEUE on a device runtime), -EIO (HIP failure, e.g. no
+ * such device), -ENOMEM. */
 int dc_init(dc_runtime **rt, const dc_config *cfg);
 
 /* Waits for pending work, frees runtime state (never user buffers). */
@@ -177,8 +194,11 @@ int dc_matrix_register(dc_runtime *rt, dc_handle *out, void *ptr, int64_t rows,
 int dc_matrix_partition(dc_runtime *rt, dc_handle m, int64_t tile,
                         dc_handle *tiles_out);
 
-/* Gathers the tiles back: waits for their pending tasks, drops the tile
- * handles.  Errors: -ENOENT, -EINVAL (not partitioned). */
+/* Gathers the tiles back: flushes pending tasks if any touch them (the
+ * graph's dependencies are fixed at that point), then drops the tile
+ * handles; a flushed graph keeps running (its tasks hold the addresses, and
+ * later graphs run after it in stream order).
+ * Errors: -ENOENT, -EINVAL (not partitioned). */
 int dc_matrix_unpartition(dc_runtime *rt, dc_handle m);
 
 /* Number of tile rows and columns of a partitioned matrix. */
@@ -202,23 +222,27 @@ int dc_task_submit(dc_runtime *rt, dc_kind kind, int nbuf, const dc_handle *bufs
                    const dc_mode *modes, const void *cl_args, size_t cl_args_size,
                    int priority);
 
-/* Starts executing every submitted task (one persistent kernel launch on the
- * runtime's stream) without waiting.  Submissions after a flush form a new
+/* Starts executing every submitted task (the executor's launches, ordered on
+ * the runtime's stream) without waiting for them.  It first waits for the
+ * previously flushed graph, if any.  Submissions after a flush form a new
  * graph that runs after the flushed one. */
 int dc_flush(dc_runtime *rt);
 
 /* Blocks until every submitted task has completed (Sections 2 and 3.3).
- * Errors: -ETIMEDOUT (watchdog), -EIO, -ENODEV (host-only runtime with
- * pending tasks; the tasks are discarded). */
+ * Errors: -EIO, -ENODEV (host-only runtime with pending tasks; the tasks are
+ * discarded). */
 int dc_wait_all(dc_runtime *rt);
 
 /* Makes a handle's data valid for the host to access (Section 3.4's
- * acquire): waits for the tasks that write it (mode R) or that touch it
- * (mode W/RW).  dc_release ends the access. */
+ * acquire): if tasks that touch the handle (or one of its tiles) are
+ * pending or in the flushed graph that may still run, it waits for every
+ * submitted task (dc_wait_all); otherwise it returns at once.  dc_release
+ * ends the access. */
 int dc_acquire(dc_runtime *rt, dc_handle h, dc_mode mode);
 int dc_release(dc_runtime *rt, dc_handle h);
 
-/* Waits for the tasks that touch h, then forgets it (and its tiles). */
+/* Waits for the tasks that touch h (as dc_acquire), then forgets it (and
+ * its tiles). */
 int dc_unregister(dc_runtime *rt, dc_handle h);
 
 /* Numerical status of a matrix handle after its tasks completed: 0, or the
@@ -259,13 +283,16 @@ int dc_graph_preds(dc_runtime *rt, int64_t t, int64_t *preds, int64_t cap,
 int dc_trace_get(dc_runtime *rt, int64_t t, int64_t *start_ns, int64_t *end_ns,
                  int32_t *worker, int32_t *kind);
 
-/* Diagnostics of the last executor launch: host time spent laying out the
- * graph (ms), work units and persistent workgroups launched.  Any output
- * pointer may be NULL. */
+/* Diagnostics of the last flushed graph: host time spent laying out the
+ * graph (ms), work units, and workgroups launched (queue executor: all
+ * classes together; level executor: the largest level).  Any output pointer
+ * may be NULL. */
 int dc_last_launch(dc_runtime *rt, double *build_ms, int64_t *units, int32_t *workers);
 
-/* Per-kernel timing.  While enabled, every launch of the two executor
- * kernels is bracketed by HIP events on the stream it is launched on; each
+/* Per-kernel timing.  While enabled, every launch of the executor's
+ * kernels is bracketed by HIP events on the stream it is launched on (queue
+ * executor: one launch per class spanning the graph; level executor: one per
+ * level and kernel); each
  * completed graph adds the measured durations and the algorithmic work of
  * the units those launches ran.  Algorithmic work per task (the operation's
  * definition, independent of how the kernel computes it): POTRF m^3/3 + m^2/2
@@ -302,8 +329,17 @@ int dc_kernel_stats_get(dc_runtime *rt, dc_kernel_stats *out);
  * TRSM_INV(i,k) (same result up to rounding; ill-conditioned diagonal tiles
  * fall back to substitution, see DC_TRSM_INV).  The runtime
  * keeps the workspace, (tiles - 1) * tile^2 doubles, until dc_shutdown;
- * -ENOMEM if it cannot be allocated. */
-int dc_potrf(dc_runtime *rt, dc_handle A, int64_t tile);
+ * -ENOMEM if it cannot be allocated.
+ * upd selects the precision of the trailing updates (the mixed-precision
+ * factor of dc_posv_ir, exposed on its own): DC_F64 as above; DC_F32 or
+ * DC_BF16: the diagonal tiles are factored in A in FP64, the off-diagonal
+ * tiles are copied to an FP32 workspace (and BF16 copies for DC_BF16),
+ * solved there with FP64 arithmetic rounded to FP32, updated with FP32 or
+ * BF16 products accumulated in FP32, and copied back into A (exactly).  The
+ * result in A is then the mixed factor whose accuracy dc_posv_ir refines;
+ * the runtime keeps that workspace (n^2 floats, n^2 BF16 values for
+ * DC_BF16, and the inverse tiles) until dc_shutdown. */
+int dc_potrf(dc_runtime *rt, dc_handle A, int64_t tile, dc_dtype upd);
 
 /* dc_potrs: solves L L^T X = B in place in B (n x r, FP64) with the factor
  * in the lower triangle of L: forward sweep TRSM_L/GEMM_RHS_N, backward
@@ -343,7 +379,7 @@ int dc_posv_ir(dc_runtime *rt, dc_handle A, dc_handle B, dc_handle X,
  * A[i] (FP64, lower triangle, in place) with tile size tiles[i] (0: the
  * matrix order, i.e. one POTRF task) and, where B != NULL and B[i] != 0,
  * solves A[i] X = B[i] in place in B[i].  All tasks of all matrices form one
- * graph executed by one set of level launches.  info_out (optional) receives
+ * graph, run by one flush of the executor.  info_out (optional) receives
  * each matrix's status (0 or the 1-based breakdown column).  Errors as for
  * dc_potrf; on an error no task runs. */
 int dc_potrf_batched(dc_runtime *rt, int64_t count, const dc_handle *A, const dc_handle *B,

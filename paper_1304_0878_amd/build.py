@@ -4,40 +4,60 @@
 
 produces ``paper_1304_0878_amd/libdagchol.so`` from the sources under
 ``paper_1304_0878_amd/csrc``.  Every HIP translation unit is compiled for
-gfx950 only, with packed FP32 instructions disabled.
+gfx950 only, with packed FP32 instructions disabled; the translation units
+are compiled in parallel into ``_build/`` and then linked.
 """
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdagchol.so")
-SOURCES = ["device.hip", "gemm_kernel.hip", "runtime.cpp", "highlevel.cpp", "ir.cpp", "batched.cpp", "serve.cpp"]
+OBJ = os.path.join(ROOT, "_build")
+SOURCES = ["device.hip", "gemm_kernel.hip", "runtime.cpp", "highlevel.cpp", "ir.cpp", "serve.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+COMPILE = [
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    "-Wno-unused-command-line-argument", "-Wl,--no-undefined",
+    "-Wno-unused-command-line-argument",
     "-I", os.path.join(ROOT, "include"),
 ]
+LINK = ["--offload-arch=gfx950", "-shared", "-fPIC", "-Wl,--no-undefined"]
 
 
 def sources():
-    return [os.path.join(CSRC, s) for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
+    return [os.path.join(CSRC, s) for s in SOURCES]
 
 
-def build(verbose=False):
-    tmp = LIB + ".tmp"
-    cmd = [HIPCC, *FLAGS, *sources(), "-o", tmp]
+def _compile(src, verbose):
+    obj = os.path.join(OBJ, os.path.basename(src) + ".o")
+    cmd = [HIPCC, *COMPILE, "-x", "hip", "-c", src, "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
-        raise RuntimeError("hipcc failed building libdagchol.so")
+        raise RuntimeError(f"hipcc failed compiling {os.path.basename(src)}")
+    return obj
+
+
+def build(verbose=False):
+    os.makedirs(OBJ, exist_ok=True)
+    jobs = min(len(SOURCES), max(1, min(8, os.cpu_count() or 1)))
+    with ThreadPoolExecutor(jobs) as ex:
+        objs = list(ex.map(lambda s: _compile(s, verbose), sources()))
+    tmp = LIB + ".tmp"
+    cmd = [HIPCC, *LINK, *objs, "-o", tmp]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        sys.stderr.write(r.stdout + r.stderr)
+        raise RuntimeError("hipcc failed linking libdagchol.so")
     os.replace(tmp, LIB)
     return LIB
 

@@ -26,6 +26,7 @@
 #include <stdint.h>
 
 #include "exec_abi.h"
+#include "queue_dev.h"
 
 using namespace dcx;
 
@@ -1234,17 +1235,59 @@ __device__ __forceinline__ uint64_t uniform_u64(uint64_t v) {
   return ((uint64_t)hi << 32) | lo;
 }
 
-// Two instances: the full one (every kind; the factorisation's and the
-// solves' units need up to about 500 registers per lane, so one workgroup
-// per CU) and a light one for levels whose units are all residual or
-// elementwise work (RESID, CAST, AXPY, SCAL), which keeps to 128 registers
-// so four workgroups share a CU and hide the memory latency these units are
-// bound by.
-// Three instances, each compiled with only the units it runs so that its
-// register allocation is its own: LI_FULL runs every kind (one workgroup
-// per CU), LI_LIGHT the residual and elementwise units, LI_RHS the
-// right-hand-side updates of the solves (both four workgroups per CU: their
-// units stream from memory).
+// The units of the panel kernel, per instance.  Three instances, each
+// compiled with only the units it runs so that its register allocation is
+// its own: LI_FULL runs every kind (the factorisation's and the solves'
+// units need up to about 500 registers per lane, so one workgroup per CU),
+// LI_LIGHT the residual and elementwise units (RESID, CAST, AXPY, SCAL) and
+// LI_RHS the right-hand-side updates of the solves (both keep to 128
+// registers, four workgroups per CU: their units stream from memory).
+template <int MODE>
+__device__ __forceinline__ void run_panel_unit(const TaskDesc &d, int u, double *lds,
+                                               int64_t *info, int32_t *failed) {
+  const int kind = __builtin_amdgcn_readfirstlane(d.kind);
+  if (MODE != LI_RHS) switch (kind) {
+    case K_SCAL: run_scal(d, u); break;
+    case K_CAST: run_cast(d, u); break;
+    case K_RESID: run_resid(d, u, lds); break;
+    case K_AXPY: run_axpy(d, u); break;
+    default: break;
+  }
+  if (MODE != LI_LIGHT) switch (kind) {
+    case K_GEMM_RHS_N:
+      if (d.ta == T_F32) run_gemm_rhs_n<float>(d, u, lds); else run_gemm_rhs_n<double>(d, u, lds);
+      break;
+    case K_GEMM_RHS_T:
+      if (d.ta == T_F32) run_gemm_rhs_t<float>(d, u, lds); else run_gemm_rhs_t<double>(d, u, lds);
+      break;
+    default: break;
+  }
+  if (MODE == LI_FULL) switch (kind) {
+    case K_TRSM_L:
+      if (d.ta == T_F32) run_trsm_l<float>(d, lds); else run_trsm_l<double>(d, lds);
+      break;
+    case K_TRSM_LT:
+      if (d.ta == T_F32) run_trsm_lt<float>(d, lds); else run_trsm_lt<double>(d, lds);
+      break;
+    case K_TRSM_L_INV: run_trsm_l_inv<true>(d, u, lds); break;
+    case K_TRSM_LT_INV: run_trsm_l_inv<false>(d, u, lds); break;
+    case K_TRSM: case K_TRSM_CAST: run_trsm(d, u, lds); break;
+    case K_TRTRI: trsm_core<true>(d, u, lds, (const gdouble *)d.a, d.lda); break;
+    case K_TRSM_INV: case K_TRSM_INV_CAST: run_trsm_inv(d, u, lds); break;
+    case K_POTRF: {
+      const int bad = run_potrf(d, lds);
+      if (bad && threadIdx.x == 0 && d.matrix >= 0) {
+        info[d.matrix] = d.row0 + bad;
+        failed[d.matrix] = 1;
+      }
+      break;
+    }
+    default: break;
+  }
+}
+
+// Level executor: the workgroups of one level launch take the level's
+// units through an atomic counter until the list is exhausted.
 template <int MODE>
 __global__ void __launch_bounds__(NT, MODE == LI_FULL ? 1 : 4) dc_level_kernel(LevelArgs A) {
   extern __shared__ double lds[];
@@ -1267,53 +1310,48 @@ __global__ void __launch_bounds__(NT, MODE == LI_FULL ? 1 : 4) dc_level_kernel(L
         atomicMin((unsigned long long *)&A.trace[3 * t], (unsigned long long)wall_clock64());
     }
     __syncthreads();
-    const int skip = __builtin_amdgcn_readfirstlane(s_skip);
-    const int kind = __builtin_amdgcn_readfirstlane(d.kind);
-    if (!skip) {
-      if (MODE != LI_RHS) switch (kind) {
-        case K_SCAL: run_scal(d, u); break;
-        case K_CAST: run_cast(d, u); break;
-        case K_RESID: run_resid(d, u, lds); break;
-        case K_AXPY: run_axpy(d, u); break;
-        default: break;
-      }
-      if (MODE != LI_LIGHT) switch (kind) {
-        case K_GEMM_RHS_N:
-          if (d.ta == T_F32) run_gemm_rhs_n<float>(d, u, lds); else run_gemm_rhs_n<double>(d, u, lds);
-          break;
-        case K_GEMM_RHS_T:
-          if (d.ta == T_F32) run_gemm_rhs_t<float>(d, u, lds); else run_gemm_rhs_t<double>(d, u, lds);
-          break;
-        default: break;
-      }
-      if (MODE == LI_FULL) switch (kind) {
-        case K_TRSM_L:
-          if (d.ta == T_F32) run_trsm_l<float>(d, lds); else run_trsm_l<double>(d, lds);
-          break;
-        case K_TRSM_LT:
-          if (d.ta == T_F32) run_trsm_lt<float>(d, lds); else run_trsm_lt<double>(d, lds);
-          break;
-        case K_TRSM_L_INV: run_trsm_l_inv<true>(d, u, lds); break;
-        case K_TRSM_LT_INV: run_trsm_l_inv<false>(d, u, lds); break;
-        case K_TRSM: case K_TRSM_CAST: run_trsm(d, u, lds); break;
-        case K_TRTRI: trsm_core<true>(d, u, lds, (const gdouble *)d.a, d.lda); break;
-        case K_TRSM_INV: case K_TRSM_INV_CAST: run_trsm_inv(d, u, lds); break;
-        case K_POTRF: {
-          const int bad = run_potrf(d, lds);
-          if (bad && tid == 0 && d.matrix >= 0) {
-            A.info[d.matrix] = d.row0 + bad;
-            A.failed[d.matrix] = 1;
-          }
-          break;
-        }
-        default: break;
-      }
-    }
+    if (!__builtin_amdgcn_readfirstlane(s_skip)) run_panel_unit<MODE>(d, u, lds, A.info, A.failed);
     if (A.trace && tid == 0) {
       atomicMax((unsigned long long *)&A.trace[3 * t + 1], (unsigned long long)wall_clock64());
       A.trace[3 * t + 2] = blockIdx.x;
     }
     __syncthreads();
+  }
+}
+
+// Ready-queue executor, panel class: thread 0 pops a ready item (queue.h),
+// the workgroup runs it, every thread's writes are released at agent scope,
+// and thread 0 completes the item (releasing successors).  The worker
+// leaves when every panel item has been claimed or the watchdog fired.
+template <int MODE>
+__global__ void __launch_bounds__(NT, MODE == LI_FULL ? 1 : 4) dc_queue_panel_kernel(QueueArgs A) {
+  extern __shared__ double lds[];
+  __shared__ uint64_t s_item;
+  __shared__ int s_skip;
+  const int tid = threadIdx.x;
+  if (tid == 0) dcq::start_worker(&A.q, A.cls);
+  for (;;) {
+    if (tid == 0) s_item = dcq::pop_item(&A.q, A.cls);
+    __syncthreads();
+    const uint64_t item = uniform_u64(s_item);
+    if (!item) break;
+    const int64_t t = dcq::item_task(item);
+    const int u = dcq::item_unit(item);
+    const TaskDesc &d = A.desc[t];
+    if (tid == 0) {
+      s_skip = (d.matrix >= 0) ? A.failed[d.matrix] : 0;
+      if (A.trace)
+        atomicMin((unsigned long long *)&A.trace[3 * t], (unsigned long long)wall_clock64());
+    }
+    __syncthreads();
+    if (!__builtin_amdgcn_readfirstlane(s_skip)) run_panel_unit<MODE>(d, u, lds, A.info, A.failed);
+    if (A.trace && tid == 0) {
+      atomicMax((unsigned long long *)&A.trace[3 * t + 1], (unsigned long long)wall_clock64());
+      A.trace[3 * t + 2] = blockIdx.x;
+    }
+    dcq::DevAT::fence_rel();
+    __syncthreads();
+    if (tid == 0) dcq::complete_item(&A.q, t);
   }
 }
 
@@ -1350,11 +1388,28 @@ int dcx_launch_level(const LevelArgs &args, int workers, size_t lds_bytes, int i
   return (int)hipGetLastError();
 }
 
+int dcx_launch_queue_panel(const QueueArgs &args, int workers, size_t lds_bytes, int inst,
+                           void *stream) {
+  if (inst == LI_LIGHT)
+    hipLaunchKernelGGL(dc_queue_panel_kernel<LI_LIGHT>, dim3(workers), dim3(NT), lds_bytes,
+                       (hipStream_t)stream, args);
+  else if (inst == LI_RHS)
+    hipLaunchKernelGGL(dc_queue_panel_kernel<LI_RHS>, dim3(workers), dim3(NT), lds_bytes,
+                       (hipStream_t)stream, args);
+  else
+    hipLaunchKernelGGL(dc_queue_panel_kernel<LI_FULL>, dim3(workers), dim3(NT), lds_bytes,
+                       (hipStream_t)stream, args);
+  return (int)hipGetLastError();
+}
+
 int dcx_level_setup(void) {
   hipError_t e = hipSuccess;
   for (const void *f : {(const void *)dc_level_kernel<LI_FULL>,
                         (const void *)dc_level_kernel<LI_LIGHT>,
-                        (const void *)dc_level_kernel<LI_RHS>})
+                        (const void *)dc_level_kernel<LI_RHS>,
+                        (const void *)dc_queue_panel_kernel<LI_FULL>,
+                        (const void *)dc_queue_panel_kernel<LI_LIGHT>,
+                        (const void *)dc_queue_panel_kernel<LI_RHS>})
     if (e == hipSuccess)
       e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
                               LDS_DOUBLES * (int)sizeof(double));
@@ -1380,6 +1435,19 @@ extern "C" int dc_executor_limits(int device, int64_t *out, int n) {
   out[5] = nb;
   out[6] = (int64_t)fa.maxThreadsPerBlock;
   return 0;
+}
+
+int dcx_queue_occupancy(size_t lds_bytes, int inst, int *blocks_per_cu) {
+  int nb = 0;
+  hipError_t e =
+      inst == LI_LIGHT ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                             &nb, dc_queue_panel_kernel<LI_LIGHT>, NT, lds_bytes)
+      : inst == LI_RHS ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                             &nb, dc_queue_panel_kernel<LI_RHS>, NT, lds_bytes)
+                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                             &nb, dc_queue_panel_kernel<LI_FULL>, NT, lds_bytes);
+  *blocks_per_cu = nb;
+  return (int)e;
 }
 
 int dcx_level_occupancy(size_t lds_bytes, int inst, int *blocks_per_cu) {

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "queue.h"
+
 namespace dcx {
 
 // Task kinds: the same numbering as dc_kind in the public header.
@@ -91,6 +93,18 @@ struct LevelArgs {
   int64_t *trace;          // optional: per task start, end (clock ticks), worker
 };
 
+// Device-side view of one ready-queue executor launch: the graph's
+// descriptors and queue state (queue.h), the worker class this launch
+// serves, the per-matrix status words and the optional trace.
+struct QueueArgs {
+  const TaskDesc *desc;
+  dcq::View q;
+  int32_t cls;
+  int32_t *failed;
+  int64_t *info;
+  int64_t *trace;
+};
+
 }  // namespace dcx
 
 // Launches one level on `stream` (a hipStream_t); returns a hipError_t value.
@@ -108,5 +122,15 @@ extern "C++" int dcx_launch_gemm(const dcx::LevelArgs &args, int workers, int ta
 extern "C++" int dcx_launch_gemm_lowp(const dcx::LevelArgs &args, int workers, void *stream);
 // Allows the GEMM/SYRK kernels their dynamic LDS sizes.
 extern "C++" int dcx_gemm_setup(void);
+// Launches the ready-queue workers of the panel class (instance inst) on
+// `stream`.
+extern "C++" int dcx_launch_queue_panel(const dcx::QueueArgs &args, int workers,
+                                        size_t lds_bytes, int inst, void *stream);
+// Launches the ready-queue workers of a GEMM class (dcq::CL_G64, CL_G32 or
+// CL_LOWP, args.cls) on `stream`.
+extern "C++" int dcx_launch_queue_gemm(const dcx::QueueArgs &args, int workers, void *stream);
+// Workgroups per CU the queue panel kernel (instance inst) keeps resident
+// with lds_bytes of LDS.
+extern "C++" int dcx_queue_occupancy(size_t lds_bytes, int inst, int *blocks_per_cu);
 // Workgroups per CU the level kernel keeps resident with lds_bytes of LDS.
 extern "C++" int dcx_level_occupancy(size_t lds_bytes, int inst, int *blocks_per_cu);

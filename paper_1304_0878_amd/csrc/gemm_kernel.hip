@@ -18,6 +18,7 @@
 #include <stdint.h>
 
 #include "exec_abi.h"
+#include "queue_dev.h"
 
 using namespace dcx;
 
@@ -545,6 +546,41 @@ __device__ __forceinline__ void unit_loop(const LevelArgs &A, double *lds, RUN r
   }
 }
 
+// Ready-queue loop of a GEMM kernel: thread 0 pops a ready item of the
+// launch's class (queue.h), the workgroup runs it, every thread's writes are
+// released at agent scope and thread 0 completes the item, which releases
+// the successors whose last dependency it was.
+template <typename RUN>
+__device__ __forceinline__ void queue_loop(const QueueArgs &A, double *lds, RUN run) {
+  __shared__ uint64_t s_item;
+  __shared__ int s_skip;
+  const int tid = threadIdx.x;
+  if (tid == 0) dcq::start_worker(&A.q, A.cls);
+  for (;;) {
+    if (tid == 0) s_item = dcq::pop_item(&A.q, A.cls);
+    __syncthreads();
+    const uint64_t item = uniform_u64(s_item);
+    if (!item) break;
+    const int64_t t = dcq::item_task(item);
+    const int u = dcq::item_unit(item);
+    const TaskDesc &d = A.desc[t];
+    if (tid == 0) {
+      s_skip = (d.matrix >= 0) ? A.failed[d.matrix] : 0;
+      if (A.trace)
+        atomicMin((unsigned long long *)&A.trace[3 * t], (unsigned long long)wall_clock64());
+    }
+    __syncthreads();
+    if (!__builtin_amdgcn_readfirstlane(s_skip)) run(d, u, lds);
+    if (A.trace && tid == 0) {
+      atomicMax((unsigned long long *)&A.trace[3 * t + 1], (unsigned long long)wall_clock64());
+      A.trace[3 * t + 2] = blockIdx.x;
+    }
+    dcq::DevAT::fence_rel();
+    __syncthreads();
+    if (tid == 0) dcq::complete_item(&A.q, t);
+  }
+}
+
 // One work item of the two-half kernel: units u0 and u0 + 1 of one task, one
 // per half.  Both have the task's K and so pass the same number of
 // workgroup barriers; a half without a unit (odd unit count) only passes
@@ -574,6 +610,17 @@ __global__ void __launch_bounds__(GT, 1) dc_gemm_lowp_kernel(LevelArgs A) {
   unit_loop(A, lds, [](const TaskDesc &d, int u, double *l) { run_unit_lowp(d, u, l); });
 }
 
+template <int TA>
+__global__ void __launch_bounds__(GT64, 1) dc_queue_gemm_kernel(QueueArgs A) {
+  extern __shared__ double lds[];
+  queue_loop(A, lds, [](const TaskDesc &d, int u, double *l) { run_pair<TA>(d, u, l); });
+}
+
+__global__ void __launch_bounds__(GT, 1) dc_queue_gemm_lowp_kernel(QueueArgs A) {
+  extern __shared__ double lds[];
+  queue_loop(A, lds, [](const TaskDesc &d, int u, double *l) { run_unit_lowp(d, u, l); });
+}
+
 constexpr int GEMM_KERNEL_LDS = 2 * 2 * STAGE64 * (int)sizeof(double);   // two halves
 constexpr int GEMM_LOWP_LDS = 2 * STAGE16 * 2;   // two stages of BF16 A and B
 static_assert(GEMM_KERNEL_LDS + 64 <= 160 * 1024, "FP64 workgroup LDS");
@@ -596,6 +643,19 @@ int dcx_launch_gemm_lowp(const LevelArgs &args, int workers, void *stream) {
   return (int)hipGetLastError();
 }
 
+int dcx_launch_queue_gemm(const QueueArgs &args, int workers, void *stream) {
+  if (args.cls == dcq::CL_G64)
+    hipLaunchKernelGGL(dc_queue_gemm_kernel<T_F64>, dim3(workers), dim3(GT64), GEMM_KERNEL_LDS,
+                       (hipStream_t)stream, args);
+  else if (args.cls == dcq::CL_G32)
+    hipLaunchKernelGGL(dc_queue_gemm_kernel<T_F32>, dim3(workers), dim3(GT64), GEMM_KERNEL_LDS,
+                       (hipStream_t)stream, args);
+  else
+    hipLaunchKernelGGL(dc_queue_gemm_lowp_kernel, dim3(workers), dim3(GT), GEMM_LOWP_LDS,
+                       (hipStream_t)stream, args);
+  return (int)hipGetLastError();
+}
+
 int dcx_gemm_setup(void) {
   hipError_t e = hipFuncSetAttribute((const void *)dc_gemm_kernel<T_F64>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, GEMM_KERNEL_LDS);
@@ -604,6 +664,15 @@ int dcx_gemm_setup(void) {
                             hipFuncAttributeMaxDynamicSharedMemorySize, GEMM_KERNEL_LDS);
   if (e == hipSuccess)
     e = hipFuncSetAttribute((const void *)dc_gemm_lowp_kernel,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, GEMM_LOWP_LDS);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void *)dc_queue_gemm_kernel<T_F64>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, GEMM_KERNEL_LDS);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void *)dc_queue_gemm_kernel<T_F32>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, GEMM_KERNEL_LDS);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void *)dc_queue_gemm_lowp_kernel,
                             hipFuncAttributeMaxDynamicSharedMemorySize, GEMM_LOWP_LDS);
   return (int)e;
 }

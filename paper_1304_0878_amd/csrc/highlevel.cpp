@@ -172,14 +172,93 @@ static int inv_workspace(dc_runtime *rt, int64_t bytes) {
   return 0;
 }
 
-extern "C" int dc_potrf(dc_runtime *rt, dc_handle A, int64_t tile) {
+int dcx_submit_mixed_factor(dc_runtime *rt, int64_t T, int64_t tile,
+                            const std::vector<dc_handle> &At, const std::vector<dc_handle> &D,
+                            const std::vector<dc_handle> &W, const std::vector<dc_handle> &S,
+                            dc_dtype upd, const std::vector<dc_handle> *V);
+
+// Grows the runtime's mixed-precision factor workspace to at least `bytes`.
+static int mix_workspace(dc_runtime *rt, int64_t bytes) {
+  if (rt->mix_ws_bytes >= bytes) return 0;
+  if (rt->mix_ws) {
+    if (hipStreamSynchronize(rt->stream) != hipSuccess) return -EIO;
+    hipFree(rt->mix_ws);
+    rt->mix_ws = nullptr;
+    rt->mix_ws_bytes = 0;
+  }
+  if (hipMalloc(&rt->mix_ws, bytes) != hipSuccess) {
+    rt->mix_ws = nullptr;
+    return -ENOMEM;
+  }
+  rt->mix_ws_bytes = bytes;
+  return 0;
+}
+
+// The factorisation with low-precision trailing updates, in place in A:
+// diagonal tiles factored in A (FP64 POTRF), off-diagonal tiles copied to
+// FP32 (plus BF16 copies for upd == BF16), factored there with the mixed
+// updates, and copied back into A (exactly: FP32 values are FP64 values).
+static int potrf_mixed(dc_runtime *rt, dc_handle A, int64_t n, int64_t tile, dc_dtype upd) {
+  const int64_t T = (n + tile - 1) / tile;
+  const bool inv = tile >= 16 && T > 1;
+  auto al = [](int64_t v) { return (v + 255) / 256 * 256; };
+  const int64_t o_w = 0;
+  const int64_t o_s = al(o_w + n * n * 4);
+  const int64_t o_v = al(o_s + (upd == DC_BF16 ? n * n * 2 : 0));
+  const int64_t total = al(o_v + (inv ? (T - 1) * tile * tile * 8 : 0));
+  TRY(mix_workspace(rt, total));
+  char *base = (char *)rt->mix_ws;
+  std::vector<dc_handle> regs;
+  auto reg = [&](dc_handle *h, void *ptr, int64_t rows, int64_t cols, int64_t ld, dc_dtype t) {
+    int e = dc_matrix_register(rt, h, ptr, rows, cols, ld, t);
+    if (e) return e;
+    regs.push_back(*h);
+    rt->handles[*h - 1].status_root = A;   // workspace tasks report into A's status
+    return 0;
+  };
+  dc_handle hW = 0, hS = 0, hV = 0;
+  int e = reg(&hW, base + o_w, n, n, n, DC_F32);
+  if (!e && upd == DC_BF16) e = reg(&hS, base + o_s, n, n, n, DC_BF16);
+  if (!e && inv) e = reg(&hV, base + o_v, (T - 1) * tile, tile, tile, DC_F64);
+  {
+    Tiles ta, tw, ts, tv;
+    if (!e) e = ta.open(rt, A, tile);
+    if (!e) e = tw.open(rt, hW, tile);
+    if (!e && hS) e = ts.open(rt, hS, tile);
+    if (!e && hV) e = tv.open(rt, hV, tile);
+    if (!e) {
+      std::vector<dc_handle> D(T), S(T * T, 0), V;
+      for (int64_t k = 0; k < T; ++k) D[k] = ta.at(k, k);
+      if (hS) S = ts.ids;
+      if (hV) for (int64_t k = 0; k + 1 < T; ++k) V.push_back(tv.at(k, 0));
+      e = dcx_submit_mixed_factor(rt, T, tile, ta.ids, D, tw.ids, S, upd, hV ? &V : nullptr);
+      for (int64_t i = 1; i < T && !e; ++i)
+        for (int64_t j = 0; j < i && !e; ++j)
+          e = submit2(rt, DC_CAST, tw.at(i, j), DC_R, ta.at(i, j), DC_W, 2);
+      if (e) dcx_discard_pending(rt);
+      else e = dc_wait_all(rt);
+    }
+  }
+  for (auto it = regs.rbegin(); it != regs.rend(); ++it) {
+    const int e2 = dc_unregister(rt, *it);
+    if (!e) e = e2;
+  }
+  return e;
+}
+
+extern "C" int dc_potrf(dc_runtime *rt, dc_handle A, int64_t tile, dc_dtype upd) {
   if (!rt) return -EINVAL;
   Handle *p = rt->get(A);
   if (!p) return -ENOENT;
-  if (p->rows != p->cols || p->dtype != DC_F64 || tile < 1 || tile > dcx::MAX_TILE)
+  if (p->rows != p->cols || p->dtype != DC_F64 || tile < 1 || tile > dcx::MAX_TILE ||
+      (upd != DC_F64 && upd != DC_F32 && upd != DC_BF16))
     return -EINVAL;
   if (p->partitioned) return -EBUSY;
   if (p->rows == 0) { p->info = 0; return 0; }
+  if (upd != DC_F64) {
+    if (rt->cfg.device < 0) return -ENODEV;
+    return potrf_mixed(rt, A, p->rows, tile, upd);
+  }
   const int64_t n = p->rows;
   const int64_t T = (n + tile - 1) / tile;
   // inverse workspaces: tiles - 1 full diagonal tiles, kept by the runtime

@@ -88,22 +88,25 @@ double now_ms() {
              std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
+}  // namespace
+
 // Submits the factorisation of A (FP64 lower, partitioned tiles At) at update
 // precision upd into the workspace: D[k] FP64 diagonal tiles, W (FP32) and S
 // (BF16) off-diagonal tile handles.  For upd == FP64 the tiles W are FP64.
 // With V (T - 1 FP64 tiles), the panel solves of column k are TRTRI(D[k])
 // into V[k] and TRSM_INV (TRSM_INV_CAST for BF16) instead of TRSM, except
 // for tile (k+1, k): it leads to the next POTRF and is solved by
-// substitution, so TRTRI runs beside it rather than ahead of it.
-int submit_mixed_factor(dc_runtime *rt, int64_t T, int64_t tile, const std::vector<dc_handle> &At,
-                        const std::vector<dc_handle> &D, const std::vector<dc_handle> &W,
-                        const std::vector<dc_handle> &S, dc_dtype upd,
-                        const std::vector<dc_handle> *V) {
+// substitution, so TRTRI runs beside it rather than ahead of it.  When D[k]
+// is A's own diagonal tile (factored in place) no copy is made.
+int dcx_submit_mixed_factor(dc_runtime *rt, int64_t T, int64_t tile,
+                            const std::vector<dc_handle> &At, const std::vector<dc_handle> &D,
+                            const std::vector<dc_handle> &W, const std::vector<dc_handle> &S,
+                            dc_dtype upd, const std::vector<dc_handle> *V) {
   auto a = [&](int64_t i, int64_t j) { return At[i * T + j]; };
   auto w = [&](int64_t i, int64_t j) { return W[i * T + j]; };
   auto s = [&](int64_t i, int64_t j) { return S[i * T + j]; };
   for (int64_t i = 0; i < T; ++i) {
-    TRY(submit(rt, DC_CAST, {a(i, i), D[i]}, {DC_R, DC_W}, 0));
+    if (D[i] != a(i, i)) TRY(submit(rt, DC_CAST, {a(i, i), D[i]}, {DC_R, DC_W}, 0));
     for (int64_t j = 0; j < i; ++j)
       TRY(submit(rt, DC_CAST, {a(i, j), w(i, j)}, {DC_R, DC_W}, j == 0 ? 0 : 1));
   }
@@ -137,8 +140,6 @@ int submit_mixed_factor(dc_runtime *rt, int64_t T, int64_t tile, const std::vect
   }
   return 0;
 }
-
-}  // namespace
 
 extern "C" int dc_posv_ir(dc_runtime *rt, dc_handle A, dc_handle B, dc_handle X, int64_t tile,
                           dc_dtype upd, double tol, int maxit, dc_ir_report *rep) {
@@ -212,7 +213,7 @@ extern "C" int dc_posv_ir(dc_runtime *rt, dc_handle A, dc_handle B, dc_handle X,
       int e = dc_matrix_partition(rt, hW, tile, W.data());
       if (!e && hS) e = dc_matrix_partition(rt, hS, tile, S.data());
       if (!e && hV) e = dc_matrix_partition(rt, hV, tile, V.data());
-      if (!e) e = submit_mixed_factor(rt, T, tile, At, D, W, S, prec, hV ? &V : nullptr);
+      if (!e) e = dcx_submit_mixed_factor(rt, T, tile, At, D, W, S, prec, hV ? &V : nullptr);
       if (!e && hVl) e = submit(rt, DC_TRTRI, {D[T - 1], hVl}, {DC_R, DC_W}, 0);
       if (!e) e = dc_wait_all(rt);
       if (hV) dc_matrix_unpartition(rt, hV);

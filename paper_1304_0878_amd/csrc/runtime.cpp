@@ -23,6 +23,7 @@
 
 #include "../../include/dagchol.h"
 #include "exec_abi.h"
+#include "queue_layout.h"
 #include "runtime_internal.h"
 
 using namespace dcx;
@@ -99,6 +100,7 @@ extern "C" void dc_config_default(dc_config *cfg) {
   memset(cfg, 0, sizeof(*cfg));
   cfg->device = 0;
   cfg->watchdog_ms = 60000;
+  cfg->executor = DC_EXEC_LEVELS;
 }
 
 extern "C" int dc_init(dc_runtime **out, const dc_config *cfg) {
@@ -107,6 +109,15 @@ extern "C" int dc_init(dc_runtime **out, const dc_config *cfg) {
   dc_config c;
   if (cfg) c = *cfg; else dc_config_default(&c);
   if (c.watchdog_ms <= 0) c.watchdog_ms = 60000;
+  if (c.executor != DC_EXEC_QUEUE && c.executor != DC_EXEC_LEVELS) return -EINVAL;
+  // The ready-queue executor's first run on the GPU did not complete (the
+  // first graph of its tests was still running after 120 s, although every
+  // wait of its protocol is bounded by the watchdog); until that is
+  // explained it is not launched.  Host-only runtimes still lay graphs out.
+  if (c.executor == DC_EXEC_QUEUE && c.device >= 0) {
+    g_last_error = "the ready-queue executor is disabled";
+    return -ENOSYS;
+  }
   dc_runtime *rt = new (std::nothrow) dc_runtime();
   if (!rt) return -ENOMEM;
   rt->cfg = c;
@@ -160,9 +171,12 @@ extern "C" int dc_shutdown(dc_runtime *rt) {
     err = dc_wait_all(rt);
     free_device(rt);
     if (rt->inv_ws) hipFree(rt->inv_ws);
+    if (rt->mix_ws) hipFree(rt->mix_ws);
     for (hipEvent_t e : rt->events) hipEventDestroy(e);
     for (hipEvent_t e : rt->tevents) hipEventDestroy(e);
     if (rt->side) hipStreamDestroy(rt->side);
+    if (rt->side2) hipStreamDestroy(rt->side2);
+    if (rt->side3) hipStreamDestroy(rt->side3);
     if (rt->own_stream) hipStreamDestroy(rt->stream);
   }
   delete rt;
@@ -210,12 +224,18 @@ extern "C" int dc_handle_lookup(dc_runtime *rt, const void *ptr, dc_handle *out)
   return 0;
 }
 
-static bool has_pending(dc_runtime *rt, dc_handle h) {
+// True while tasks that touch h (or one of its tiles) are pending
+// (submitted, not flushed) or, with inflight, part of the flushed graph that
+// may still run.  Dropping tile handles only needs the pending ones to have
+// been laid out (later graphs run after the flushed one in stream order);
+// giving the data to the host or back to its owner needs the flushed graph
+// to have finished too.
+static bool has_pending(dc_runtime *rt, dc_handle h, bool inflight) {
   Handle *p = rt->get(h);
   if (!p) return false;
-  if (p->pending) return true;
+  if (p->pending || (inflight && rt->inflight && p->inflight_ref)) return true;
   for (dc_handle t : p->tiles)
-    if (has_pending(rt, t)) return true;
+    if (has_pending(rt, t, inflight)) return true;
   return false;
 }
 
@@ -276,8 +296,8 @@ extern "C" int dc_matrix_unpartition(dc_runtime *rt, dc_handle m) {
   Handle *p = rt->get(m);
   if (!p) return -ENOENT;
   if (!p->partitioned) return -EINVAL;
-  if (has_pending(rt, m)) {
-    int e = dc_wait_all(rt);
+  if (has_pending(rt, m, false)) {
+    int e = dc_flush(rt);
     if (e) return e;
   }
   drop_tiles(rt, m);
@@ -299,7 +319,7 @@ extern "C" int dc_unregister(dc_runtime *rt, dc_handle h) {
   Handle *p = rt->get(h);
   if (!p) return -ENOENT;
   if (p->parent) return -EINVAL;   // tiles go away with unpartition
-  if (has_pending(rt, h)) {
+  if (has_pending(rt, h, true)) {
     int e = dc_wait_all(rt);
     if (e) return e;
   }
@@ -314,7 +334,7 @@ extern "C" int dc_acquire(dc_runtime *rt, dc_handle h, dc_mode mode) {
   if (!rt) return -EINVAL;
   if (!rt->get(h)) return -ENOENT;
   if (mode != DC_R && mode != DC_W && mode != DC_RW) return -EINVAL;
-  if (has_pending(rt, h)) return dc_wait_all(rt);
+  if (has_pending(rt, h, true)) return dc_wait_all(rt);
   return 0;
 }
 
@@ -677,15 +697,26 @@ static int hip_err(hipError_t e) { return e == hipSuccess ? 0 : -EIO; }
 static int finalize(dc_runtime *rt) {
   if (!rt->inflight) return 0;
   rt->inflight = false;
+  Inflight &f = rt->fl;
+  for (dc_handle h : f.handles)
+    if (Handle *p = rt->get(h)) p->inflight_ref = false;
+  f.handles.clear();
   hipError_t e = hipStreamSynchronize(rt->stream);
   if (e != hipSuccess) return fail_hip(e, "hipStreamSynchronize");
-  Inflight &f = rt->fl;
   // status, info and failed words live at the end of the arena
   std::vector<char> tail(f.tail_bytes);
-  e = hipMemcpy(tail.data(), (char *)rt->arena_dev + f.tail_off, f.tail_bytes,
+  e = hipMemcpy(tail.data(), (char *)f.arena_dev + f.tail_off, f.tail_bytes,
                 hipMemcpyDeviceToHost);
   if (e != hipSuccess) return -EIO;
   int32_t status = 0;
+  if (f.status_off >= 0) {
+    int32_t st = 0;
+    memcpy(&st, tail.data() + (f.status_off - f.tail_off), 4);
+    if (st) {
+      g_last_error = "executor watchdog expired: no task completed for watchdog_ms";
+      status = -ETIMEDOUT;
+    }
+  }
   for (size_t s = 0; s < f.slot_roots.size(); ++s) {
     if (!f.slot_factor[s]) continue;   // only a factorisation sets the status
     int64_t info;
@@ -705,7 +736,7 @@ static int finalize(dc_runtime *rt) {
   f.timed.clear();
   if (f.trace_off) {
     rt->trace_host.resize(3 * (size_t)f.ntasks);
-    e = hipMemcpy(rt->trace_host.data(), (char *)rt->arena_dev + f.trace_off,
+    e = hipMemcpy(rt->trace_host.data(), (char *)f.arena_dev + f.trace_off,
                   rt->trace_host.size() * 8, hipMemcpyDeviceToHost);
     if (e != hipSuccess) return -EIO;
     rt->trace_t0 = INT64_MAX;
@@ -847,6 +878,283 @@ static int64_t assign_levels(dc_runtime *rt, int workers, std::vector<int32_t> &
   return nl;
 }
 
+// ------------------------------------------------- ready-queue executor
+
+// Worker class of a task: GEMM/SYRK units by input precision (each class is
+// its own kernel), everything else the panel kernel.
+static int queue_class(const TaskDesc &d) {
+  if (d.kind != K_GEMM && d.kind != K_SYRK) return dcq::CL_PANEL;
+  return d.ta == T_F64 ? dcq::CL_G64 : d.ta == T_F32 ? dcq::CL_G32 : dcq::CL_LOWP;
+}
+
+static int ensure_stream(hipStream_t *s) {
+  if (*s) return 0;
+  const hipError_t e = hipStreamCreateWithFlags(s, hipStreamNonBlocking);
+  if (e != hipSuccess) { *s = nullptr; return fail_hip(e, "hipStreamCreate"); }
+  return 0;
+}
+
+static int ensure_events(dc_runtime *rt, size_t n) {
+  while (rt->events.size() < n) {
+    hipEvent_t ev;
+    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) return -EIO;
+    rt->events.push_back(ev);
+  }
+  return 0;
+}
+
+// Lays the pending graph out for the ready-queue executor (queue.h) and
+// launches one persistent kernel per worker class present in it, all on
+// concurrent streams: the panel kernel and the GEMM kernels of each input
+// precision.  Every worker takes a whole CU (the panel and GEMM workgroups
+// use most of a CU's LDS or registers), and the classes together take at
+// most the device's CUs, so every worker of the graph is resident at once:
+// a GEMM worker waiting for a panel task never keeps the panel workers from
+// running.  Tasks without predecessors start in the rings; the others are
+// pushed by the workers that complete their last predecessor.
+static int flush_queue(dc_runtime *rt, std::chrono::steady_clock::time_point t_build0) {
+  const int64_t nt = (int64_t)rt->tasks.size();
+  std::vector<dcq::TaskIn> tin(nt);
+  double ccost[dcq::NCLASS] = {0, 0, 0, 0};
+  int64_t citems[dcq::NCLASS] = {0, 0, 0, 0};
+  bool all_light = true, all_rhs = true;
+  size_t plds = 16;
+  int64_t total_units = 0;
+  const bool timing = rt->ktiming;
+  double wflops[2] = {0, 0}, wbytes[2] = {0, 0};
+  for (int64_t t = 0; t < nt; ++t) {
+    const Task &k = rt->tasks[t];
+    const TaskDesc &d = k.desc;
+    dcq::TaskIn &q = tin[t];
+    q.preds = k.preds.data();
+    q.npreds = (int64_t)k.preds.size();
+    q.cls = queue_class(d);
+    q.paired = q.cls == dcq::CL_G64 || q.cls == dcq::CL_G32;
+    q.items = q.paired ? (d.nunits + 1) / 2 : d.nunits;
+    q.lane = k.prio;
+    ccost[q.cls] += cost_ns(d);
+    citems[q.cls] += q.items;
+    total_units += d.nunits;
+    if (q.cls == dcq::CL_PANEL) {
+      plds = std::max(plds, lds_for(d));
+      const int kd = d.kind;
+      if (!(kd == K_SCAL || kd == K_CAST || kd == K_RESID || kd == K_AXPY)) all_light = false;
+      if (!(kd == K_GEMM_RHS_N || kd == K_GEMM_RHS_T)) all_rhs = false;
+    }
+    if (timing) {
+      double fl, by;
+      task_work(d, &fl, &by);
+      wflops[q.cls != dcq::CL_PANEL] += fl;
+      wbytes[q.cls != dcq::CL_PANEL] += by;
+    }
+  }
+  dcq::Sizes sz;
+  if (dcq::layout_sizes(nt, tin.data(), sz) || total_units >= INT32_MAX) return -ENOMEM;
+  const int nslots_roots = (int)rt->slot_roots.size();
+  const bool trace = rt->cfg.trace != 0;
+
+  int64_t off = 0;
+  auto take = [&](int64_t bytes) { int64_t o = off; off = align_up(off + bytes, 256); return o; };
+  const int64_t o_desc = take(nt * (int64_t)sizeof(TaskDesc));
+  const int64_t o_ctl = take((int64_t)sizeof(dcq::Ctl));
+  const int64_t o_deps = take(nt * 4);
+  const int64_t o_left = take(nt * 4);
+  const int64_t o_soff = take((nt + 1) * 4);
+  const int64_t o_succ = take(std::max<int64_t>(sz.nedges, 1) * 4);
+  const int64_t o_meta = take(nt * 4);
+  const int64_t o_ring = take(sz.nitems * 8);
+  const int64_t o_tail = off;
+  const int64_t o_info = take(std::max(nslots_roots, 1) * 8);
+  const int64_t o_failed = take(std::max(nslots_roots, 1) * 4);
+  const int64_t o_status = take(16);
+  const int64_t tail_end = off;
+  const int64_t o_trace = trace ? take(nt * 3 * 8) : 0;
+  const int64_t total = off;
+  if (total > rt->arena_cap) {
+    free_device(rt);
+    int64_t cap = align_up(total + total / 4, 1 << 20);
+    if (hipMalloc(&rt->arena_dev, cap) != hipSuccess) { rt->arena_dev = nullptr; return -ENOMEM; }
+    if (hipHostMalloc(&rt->arena_host, cap, hipHostMallocDefault) != hipSuccess) {
+      hipFree(rt->arena_dev);
+      rt->arena_dev = nullptr;
+      rt->arena_host = nullptr;
+      return -ENOMEM;
+    }
+    rt->arena_cap = cap;
+  }
+  // CU shares.  Panel alone: its lightest instance that runs all its units,
+  // as many workgroups as fit.  Otherwise every class present gets at least
+  // one CU; the panel kernel gets its work's share of the CUs but at least
+  // PANEL_MIN_CUS (or one per item), the GEMM classes split the rest by
+  // estimated work.
+  const int phys = std::max(1, rt->num_cus);
+  const int cus = rt->cfg.workers > 0 ? std::min(rt->cfg.workers, phys) : phys;
+  std::vector<int> present;
+  for (int c = 0; c < dcq::NCLASS; ++c)
+    if (citems[c] > 0) present.push_back(c);
+  int workers[dcq::NCLASS] = {0, 0, 0, 0};
+  int inst = LI_FULL;
+  const bool panel = citems[dcq::CL_PANEL] > 0;
+  const int ngemm = (int)present.size() - (panel ? 1 : 0);
+  if (panel && ngemm == 0) {
+    inst = all_light ? LI_LIGHT : all_rhs ? LI_RHS : LI_FULL;
+    int per_cu = 1;
+    dcx_queue_occupancy(plds, inst, &per_cu);
+    workers[dcq::CL_PANEL] =
+        (int)std::min<int64_t>(citems[dcq::CL_PANEL], (int64_t)cus * std::max(1, per_cu));
+  } else {
+    const double gcost = ccost[1] + ccost[2] + ccost[3];
+    int pcus = 0;
+    if (panel) {
+      const double share = ccost[0] / std::max(1.0, ccost[0] + gcost);
+      const int floor_cus = (int)std::min<int64_t>(citems[0], PANEL_MIN_CUS);
+      pcus = std::min(std::max({1, (int)std::ceil(share * cus), floor_cus}),
+                      std::max(1, cus - ngemm));
+      workers[dcq::CL_PANEL] = (int)std::min<int64_t>(citems[0], pcus);
+    }
+    const int rest = std::max(ngemm, cus - pcus);
+    int given = 0, last = -1;
+    for (int c = 1; c < dcq::NCLASS; ++c) {
+      if (!citems[c]) continue;
+      const int share = std::max(1, (int)std::floor(rest * ccost[c] / std::max(1.0, gcost)));
+      workers[c] = share;
+      given += share;
+      last = c;
+    }
+    if (last >= 0 && given < rest) workers[last] += rest - given;
+    for (int c = 1; c < dcq::NCLASS; ++c)
+      workers[c] = (int)std::min<int64_t>(citems[c], workers[c]);
+  }
+  char *hb = (char *)rt->arena_host;
+  TaskDesc *desc = (TaskDesc *)(hb + o_desc);
+  for (int64_t t = 0; t < nt; ++t) desc[t] = rt->tasks[t].desc;
+  const int64_t ticks = (int64_t)std::min<double>(
+      (double)rt->cfg.watchdog_ms * (double)rt->wall_clock_khz, 9.0e18);
+  int64_t launched[dcq::NCLASS];
+  for (int c = 0; c < dcq::NCLASS; ++c) launched[c] = workers[c];
+  // a worker idle for 20 ms while another class's workers have not started
+  // may give up its CU (queue.h, Residency)
+  const int64_t yield_ticks = (int64_t)20 * rt->wall_clock_khz;
+  dcq::layout_fill(nt, tin.data(), sz, ticks, yield_ticks, launched,
+                   {(dcq::Ctl *)(hb + o_ctl), (int32_t *)(hb + o_deps), (int32_t *)(hb + o_left),
+                    (int32_t *)(hb + o_soff), (int32_t *)(hb + o_succ), (uint32_t *)(hb + o_meta),
+                    (uint64_t *)(hb + o_ring)});
+  memset(hb + o_info, 0, std::max(nslots_roots, 1) * 8);
+  memset(hb + o_failed, 0, std::max(nslots_roots, 1) * 4);
+  memset(hb + o_status, 0, 16);
+  if (trace) {
+    int64_t *tr = (int64_t *)(hb + o_trace);
+    for (int64_t t = 0; t < nt; ++t) { tr[3 * t] = INT64_MAX; tr[3 * t + 1] = 0; tr[3 * t + 2] = -1; }
+  }
+  rt->last_build_ms =
+      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_build0).count();
+
+  hipError_t e = hipMemcpyAsync(rt->arena_dev, rt->arena_host, total, hipMemcpyHostToDevice,
+                                rt->stream);
+  if (e != hipSuccess) return fail_hip(e, "hipMemcpyAsync(graph)");
+  char *db = (char *)rt->arena_dev;
+  QueueArgs a;
+  a.desc = (const TaskDesc *)(db + o_desc);
+  a.q.ctl = (dcq::Ctl *)(db + o_ctl);
+  a.q.deps = (int32_t *)(db + o_deps);
+  a.q.left = (int32_t *)(db + o_left);
+  a.q.soff = (const int32_t *)(db + o_soff);
+  a.q.succ = (const int32_t *)(db + o_succ);
+  a.q.meta = (const uint32_t *)(db + o_meta);
+  a.q.ring = (uint64_t *)(db + o_ring);
+  a.q.status = (int32_t *)(db + o_status);
+  a.failed = (int32_t *)(db + o_failed);
+  a.info = (int64_t *)(db + o_info);
+  a.trace = trace ? (int64_t *)(db + o_trace) : nullptr;
+
+  // one stream per class launched: the first GEMM class on the runtime's
+  // stream, the panel kernel on the side stream, further classes on their
+  // own streams
+  hipStream_t cstream[dcq::NCLASS] = {nullptr, nullptr, nullptr, nullptr};
+  {
+    hipStream_t extra[2] = {nullptr, nullptr};
+    int used_main = 0, nextra = 0;
+    if (rt->side2 == nullptr || rt->side3 == nullptr) {
+      int er = ensure_stream(&rt->side2);
+      if (!er) er = ensure_stream(&rt->side3);
+      if (er) return er;
+    }
+    extra[0] = rt->side2;
+    extra[1] = rt->side3;
+    for (int c : present) {
+      if (c == dcq::CL_PANEL) cstream[c] = ngemm ? rt->side : rt->stream;
+      else if (!used_main) { cstream[c] = rt->stream; used_main = 1; }
+      else cstream[c] = extra[nextra++];
+    }
+  }
+  const size_t nfork = present.size() > 1 ? present.size() : 0;
+  if (nfork && ensure_events(rt, 1 + nfork)) return -EIO;
+  if (nfork) {
+    hipEventRecord(rt->events[0], rt->stream);
+    for (int c : present)
+      if (cstream[c] != rt->stream) hipStreamWaitEvent(cstream[c], rt->events[0], 0);
+  }
+  size_t ntev = 0;
+  std::vector<Inflight::Timed> timed;
+  auto tev = [&](hipStream_t st) -> size_t {
+    while (rt->tevents.size() <= ntev) {
+      hipEvent_t ev;
+      if (hipEventCreate(&ev) != hipSuccess) return SIZE_MAX;
+      rt->tevents.push_back(ev);
+    }
+    if (hipEventRecord(rt->tevents[ntev], st) != hipSuccess) return SIZE_MAX;
+    return ntev++;
+  };
+  int max_workers = 0;
+  // the panel kernel first: its workgroups then hold their CUs before the
+  // GEMM workers spread over the rest
+  for (int c : present) {
+    a.cls = c;
+    const size_t tb = timing ? tev(cstream[c]) : 0;
+    const int le = c == dcq::CL_PANEL
+                       ? dcx_launch_queue_panel(a, workers[c], plds, inst, cstream[c])
+                       : dcx_launch_queue_gemm(a, workers[c], cstream[c]);
+    if (le != 0) return fail_hip((hipError_t)le, "queue executor launch");
+    if (timing) {
+      const size_t te = tev(cstream[c]);
+      if (tb == SIZE_MAX || te == SIZE_MAX) return -EIO;
+      const int k = c != dcq::CL_PANEL;
+      timed.push_back({tb, te, k, wflops[k], wbytes[k]});
+      wflops[k] = wbytes[k] = 0.0;   // a second GEMM class's launch adds nothing twice
+    }
+    max_workers += workers[c];
+  }
+  if (nfork) {
+    size_t j = 1;
+    for (int c : present)
+      if (cstream[c] != rt->stream) {
+        hipEventRecord(rt->events[j], cstream[c]);
+        hipStreamWaitEvent(rt->stream, rt->events[j], 0);
+        ++j;
+      }
+  }
+  Inflight &f = rt->fl;
+  f.arena_dev = rt->arena_dev;
+  f.tail_off = o_tail;
+  f.tail_bytes = tail_end - o_tail;
+  f.status_off = o_status;
+  f.info_off = o_info;
+  f.trace_off = o_trace;
+  f.ntasks = nt;
+  f.slot_roots = rt->slot_roots;
+  f.slot_factor = rt->slot_factor;
+  f.kinds.resize(nt);
+  for (int64_t t = 0; t < nt; ++t) f.kinds[t] = rt->tasks[t].desc.kind;
+  f.handles = rt->touched;
+  for (dc_handle h : f.handles) rt->handles[h - 1].inflight_ref = true;
+  f.timed = std::move(timed);
+  rt->inflight = true;
+  rt->last_units = total_units;
+  rt->last_workers = max_workers;
+  rt->last_levels = 1;
+  return 0;
+}
+
 extern "C" int dc_flush(dc_runtime *rt) {
   if (!rt) return -EINVAL;
   if (rt->tasks.empty()) return 0;
@@ -860,6 +1168,11 @@ extern "C" int dc_flush(dc_runtime *rt) {
   int err = finalize(rt);
   if (err) { drop(); return err; }
   auto t_build0 = std::chrono::steady_clock::now();
+  if (rt->cfg.executor == DC_EXEC_QUEUE && !rt->ext) {
+    err = flush_queue(rt, t_build0);
+    drop();
+    return err;
+  }
   const int64_t nt = (int64_t)rt->tasks.size();
   const int workers_cfg = rt->cfg.workers > 0 ? rt->cfg.workers : rt->num_cus;
   std::vector<int32_t> level;
@@ -914,7 +1227,16 @@ extern "C" int dc_flush(dc_runtime *rt) {
   const int64_t o_trace = trace ? take(nt * 3 * 8) : 0;
   const int64_t total = off;
 
-  if (total > rt->arena_cap) {
+  // the graph's device layout goes to the runtime's arena, or to the
+  // caller's fixed buffers when the call may not allocate
+  const ExtArena *ext = rt->ext;
+  if (ext) {
+    if (total > ext->cap) {
+      g_last_error = "graph layout exceeds the fixed scratch buffer";
+      drop();
+      return -ENOMEM;
+    }
+  } else if (total > rt->arena_cap) {
     free_device(rt);
     int64_t cap = align_up(total + total / 4, 1 << 20);
     if (hipMalloc(&rt->arena_dev, cap) != hipSuccess) { rt->arena_dev = nullptr; drop(); return -ENOMEM; }
@@ -927,7 +1249,8 @@ extern "C" int dc_flush(dc_runtime *rt) {
     }
     rt->arena_cap = cap;
   }
-  char *hb = (char *)rt->arena_host;
+  void *const arena_dev = ext ? ext->dev : rt->arena_dev;
+  char *hb = ext ? (char *)ext->host : (char *)rt->arena_host;
   TaskDesc *desc = (TaskDesc *)(hb + o_desc);
   uint64_t *items = (uint64_t *)(hb + o_items);
   std::vector<int64_t> lbegin(nl, 0);
@@ -986,10 +1309,9 @@ extern "C" int dc_flush(dc_runtime *rt) {
   auto t_build1 = std::chrono::steady_clock::now();
   rt->last_build_ms = std::chrono::duration<double, std::milli>(t_build1 - t_build0).count();
 
-  hipError_t e = hipMemcpyAsync(rt->arena_dev, rt->arena_host, total, hipMemcpyHostToDevice,
-                                rt->stream);
+  hipError_t e = hipMemcpyAsync(arena_dev, hb, total, hipMemcpyHostToDevice, rt->stream);
   if (e != hipSuccess) { drop(); return fail_hip(e, "hipMemcpyAsync(graph)"); }
-  char *db = (char *)rt->arena_dev;
+  char *db = (char *)arena_dev;
   int max_workers = 0;
   size_t nevents = 0, ntev = 0;
   std::vector<Inflight::Timed> timed;
@@ -1041,7 +1363,9 @@ extern "C" int dc_flush(dc_runtime *rt) {
     const int gcus = hasp ? std::max(1, cus - pcus) : cus;
     int gworkers = 0;
     hipStream_t pstream = rt->stream;
-    if (hasp && hasg) {
+    // with fixed buffers both kernels of a level run on the runtime's
+    // stream, one after the other (no events to create)
+    if (hasp && hasg && !ext) {
       // fork: the panel units run on the side stream next to the GEMM units
       while (rt->events.size() < nevents + 2) {
         hipEvent_t ev;
@@ -1089,7 +1413,7 @@ extern "C" int dc_flush(dc_runtime *rt) {
         timed.push_back({tb, te, 1, wflops[2 * L + 1], wbytes[2 * L + 1]});
       }
     }
-    if (hasp && hasg) {
+    if (hasp && hasg && !ext) {
       // join
       hipEventRecord(rt->events[nevents + 1], rt->side);
       hipStreamWaitEvent(rt->stream, rt->events[nevents + 1], 0);
@@ -1098,6 +1422,7 @@ extern "C" int dc_flush(dc_runtime *rt) {
     max_workers = std::max(max_workers, pworkers + gworkers);
   }
   Inflight &f = rt->fl;
+  f.arena_dev = arena_dev;
   f.tail_off = o_tail;
   f.tail_bytes = tail_end - o_tail;
   f.status_off = -1;
@@ -1108,6 +1433,8 @@ extern "C" int dc_flush(dc_runtime *rt) {
   f.slot_factor = rt->slot_factor;
   f.kinds.resize(nt);
   for (int64_t t = 0; t < nt; ++t) f.kinds[t] = rt->tasks[t].desc.kind;
+  f.handles = rt->touched;
+  for (dc_handle h : f.handles) rt->handles[h - 1].inflight_ref = true;
   f.timed = std::move(timed);
   rt->inflight = true;
   rt->last_units = total_units;
@@ -1133,6 +1460,7 @@ extern "C" const char *dc_strerror(int err) {
     case -ENOMEM: return "out of memory or capacity";
     case -ENODEV: return "no device: host-only runtime cannot execute tasks";
     case -ETIMEDOUT: return "executor watchdog expired";
+    case -ENOSYS: return "feature disabled";
     case -EIO: return "HIP runtime error";
     default: return "unknown error";
   }

@@ -42,6 +42,8 @@ struct Handle {
   int64_t last_writer = -1;
   std::vector<int64_t> readers;
   int pending = 0;
+  // referenced by the graph that was flushed and may still be running
+  bool inflight_ref = false;
   // numerical status of the last factorisation (top-level handles)
   int64_t info = 0;
   // top-level handle whose numerical status this handle's tasks share (0:
@@ -56,12 +58,22 @@ struct Task {
   int prio = 0;
 };
 
+// Fixed buffers for a graph's layout (the calls that may not allocate):
+// device memory of cap bytes and a host staging area of the same size.
+struct ExtArena {
+  void *dev = nullptr;
+  void *host = nullptr;
+  int64_t cap = 0;
+};
+
 struct Inflight {
+  void *arena_dev = nullptr;       // where the graph's layout lives
   int64_t tail_off = 0, tail_bytes = 0, status_off = 0, info_off = 0, trace_off = 0;
   int64_t ntasks = 0;
   std::vector<dc_handle> slot_roots;
   std::vector<char> slot_factor;   // slot has a POTRF task in the graph
   std::vector<int32_t> kinds;
+  std::vector<dc_handle> handles;  // handles the flushed graph references
   // timed launches: (begin event, end event, kernel class, flops, bytes)
   struct Timed { size_t b, e; int cls; double flops, bytes; };
   std::vector<Timed> timed;
@@ -71,6 +83,7 @@ struct dc_runtime {
   dc_config cfg{};
   hipStream_t stream = nullptr;
   hipStream_t side = nullptr;                  // panel units next to GEMM units
+  hipStream_t side2 = nullptr, side3 = nullptr; // further concurrent worker classes
   std::vector<hipEvent_t> events;              // fork/join events, reused per flush
   bool ktiming = false;                        // per-kernel timing enabled
   std::vector<hipEvent_t> tevents;             // timing events, reused per flush
@@ -92,10 +105,13 @@ struct dc_runtime {
   void *arena_dev = nullptr;
   void *inv_ws = nullptr;                      // dc_potrf's inverse workspace
   int64_t inv_ws_bytes = 0;
+  void *mix_ws = nullptr;                      // dc_potrf's mixed-precision workspace
+  int64_t mix_ws_bytes = 0;
   void *arena_host = nullptr;
   int64_t arena_cap = 0;
   bool inflight = false;
   Inflight fl;
+  const ExtArena *ext = nullptr;               // set for the duration of a no-alloc call
 
   std::vector<int64_t> trace_host;
   std::vector<int32_t> trace_kind;

@@ -26,6 +26,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 dc_handle = ctypes.c_int64
 DC_R, DC_W, DC_RW = 1, 2, 3
 DC_F64, DC_F32, DC_BF16 = 0, 1, 2
+DC_EXEC_LEVELS, DC_EXEC_QUEUE = 0, 1
 (DC_POTRF, DC_TRSM, DC_SYRK, DC_GEMM, DC_TRSM_L, DC_GEMM_RHS_N, DC_TRSM_LT, DC_GEMM_RHS_T,
  DC_SCAL, DC_CAST, DC_RESID, DC_AXPY, DC_TRSM_CAST, DC_TRTRI, DC_TRSM_INV,
  DC_TRSM_INV_CAST, DC_TRSM_L_INV, DC_TRSM_LT_INV) = range(18)
@@ -36,7 +37,8 @@ ERRNO = {22: "EINVAL", 2: "ENOENT", 16: "EBUSY", 12: "ENOMEM", 19: "ENODEV", 110
 
 class dc_config(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int), ("stream", ctypes.c_void_p), ("workers", ctypes.c_int),
-                ("watchdog_ms", ctypes.c_int64), ("trace", ctypes.c_int)]
+                ("watchdog_ms", ctypes.c_int64), ("trace", ctypes.c_int),
+                ("executor", ctypes.c_int)]
 
 
 class dc_graph_stats(ctypes.Structure):
@@ -112,7 +114,7 @@ _SIGS = {
     "dc_graph_stats_get": (ctypes.c_int, [_P, ctypes.POINTER(dc_graph_stats)]),
     "dc_graph_preds": (ctypes.c_int, [_P, _I64, _PI64, _I64, _PI64]),
     "dc_trace_get": (ctypes.c_int, [_P, _I64, _PI64, _PI64, _PI32, _PI32]),
-    "dc_potrf": (ctypes.c_int, [_P, _H, _I64]),
+    "dc_potrf": (ctypes.c_int, [_P, _H, _I64, ctypes.c_int]),
     "dc_potrs": (ctypes.c_int, [_P, _H, _H, _I64]),
     "dc_posv_ir": (ctypes.c_int, [_P, _H, _H, _H, _I64, ctypes.c_int, ctypes.c_double,
                                   ctypes.c_int, ctypes.POINTER(dc_ir_report)]),
@@ -167,13 +169,15 @@ class Runtime:
     """One dc_runtime.  device=-1 makes a host-only runtime (graph building
     and inspection, no execution)."""
 
-    def __init__(self, device=0, stream=None, workers=0, watchdog_ms=60000, trace=False):
+    def __init__(self, device=0, stream=None, workers=0, watchdog_ms=60000, trace=False,
+                 executor=DC_EXEC_LEVELS):
         cfg = dc_config()
         _lib.dc_config_default(ctypes.byref(cfg))
         cfg.device = device
         cfg.workers = workers
         cfg.watchdog_ms = watchdog_ms
         cfg.trace = 1 if trace else 0
+        cfg.executor = executor
         if device >= 0:
             import torch
             s = stream if stream is not None else torch.cuda.current_stream(device)
@@ -316,8 +320,8 @@ class Runtime:
                 for k in ("panel", "gemm")}
 
     # -- high level
-    def dc_potrf(self, a, tile):
-        _check(_lib.dc_potrf(self._ptr, a, tile), "dc_potrf")
+    def dc_potrf(self, a, tile, upd=DC_F64):
+        _check(_lib.dc_potrf(self._ptr, a, tile, upd), "dc_potrf")
 
     def dc_potrs(self, l, b, tile):
         _check(_lib.dc_potrs(self._ptr, l, b, tile), "dc_potrs")
@@ -366,11 +370,12 @@ _track_meta()
 
 # ------------------------------------------------------ tensor-level helpers
 
-def potrf(rt, a, tile):
-    """Factors the lower triangle of a CUDA float64 tensor in place; returns info."""
+def potrf(rt, a, tile, upd=DC_F64):
+    """Factors the lower triangle of a CUDA float64 tensor in place (trailing
+    updates at precision ``upd``); returns info."""
     h = rt.register_tensor(a)
     try:
-        rt.dc_potrf(h, tile)
+        rt.dc_potrf(h, tile, upd)
         return rt.dc_get_info(h)
     finally:
         rt.dc_unregister(h)

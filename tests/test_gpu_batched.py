@@ -106,3 +106,24 @@ def test_batched_integer_exact(dc, rt, torch_dev):
     assert infos == [0, 0, 0, 0]
     for (l0, x0), l, x in zip(sols, ls, xs):
         assert np.array_equal(l, l0) and np.array_equal(x, x0)
+
+
+def test_batched_at_tuner_tiles_matches_oracle(dc, rt, torch_dev):
+    """The configuration the benchmark times: orders drawn from [16, 512] and
+    the tile sizes the committed autotuner cache picks for them (for every
+    bucket up to 512 the whole matrix, so the solves run the substitution
+    TRSM_L / TRSM_LT units on diagonal tiles of order up to 512)."""
+    from paper_1304_0878_amd import tune
+    cache = tune.load()
+    assert cache is not None
+    ns, mats, rhs = _batch(64, 5, nmax=512)
+    tiles = tune.tiles_for(ns, cache)
+    assert sum(1 for n, t in zip(ns, tiles) if (t or n) > 128) >= 20
+    infos, ls, xs = _run(dc, rt, torch_dev, mats, rhs, tiles)
+    assert infos == [0] * len(ns)
+    for a, b, l, x, t in zip(mats, rhs, ls, xs, tiles):
+        n = a.shape[0]
+        assert core.backward_error_fro(a, l) <= 1e-13
+        lr = np.tril(core.potrf_tiled(a, t or n)[0])
+        xr = core.potrs_tiled(lr, b, t or n)
+        assert np.abs(x - xr).max() / np.abs(xr).max() <= 16 * n * U * np.linalg.cond(a)

@@ -198,3 +198,54 @@ def test_posv_ir_many_tiles(dc, rt, torch_dev):
     xref = mixed.reference_solution(a, bm, 64)
     assert rep["converged"] == 1, rep
     assert np.abs(x - xref).max() / np.abs(xref).max() <= 1e-10
+
+
+# ------------------------------------------- the mixed factor on its own
+
+# Backward errors of the GPU's mixed factor, filled in by the test below and
+# printed at the end of the module (pytest -s shows them).
+MIXED_ETA = {}
+
+
+@pytest.mark.parametrize("upd", ["f32", "bf16"])
+@pytest.mark.parametrize("n,tile", [(256, 128), (1024, 256), (2048, 256)])
+def test_mixed_factor_backward_error_within_4x_of_emulation(dc, rt, torch_dev, upd, n, tile):
+    """dc_potrf with FP32/BF16 updates: the factor's backward error
+    ||A - L L^T||_F / ||A||_F (long double) is at most 4 times that of the
+    oracle's numpy emulation of the same mixed scheme (FP32 off-diagonal
+    storage, BF16-rounded inputs for BF16, FP32 accumulation)."""
+    a = inputs.spd_normal(n, 21, 1e-2)
+    ta = _t(torch_dev, a)
+    u = dc.DC_F32 if upd == "f32" else dc.DC_BF16
+    assert dc.potrf(rt, ta, tile, upd=u) == 0
+    l = np.tril(ta.cpu().numpy())
+    eta_gpu = core.backward_error_fro(a, l)
+    l_emu, info = mixed.mixed_factor(a, tile, upd)
+    assert info == 0
+    eta_emu = core.backward_error_fro(a, l_emu)
+    MIXED_ETA[(upd, n)] = (eta_gpu, eta_emu)
+    print(f"mixed factor {upd} n={n} tile={tile}: eta_gpu={eta_gpu:.3e} eta_emulation={eta_emu:.3e}")
+    assert eta_gpu <= 4 * eta_emu
+    # the off-diagonal part holds FP32 values
+    off = np.tril(l, -tile)
+    assert np.array_equal(off, off.astype(np.float32).astype(np.float64))
+
+
+@pytest.mark.parametrize("upd", ["f32", "bf16"])
+def test_mixed_factor_exact_on_integer_factor(dc, rt, torch_dev, upd):
+    """A = L0 L0^T with integer L0 (entries within BF16 and FP32 exactness):
+    the mixed factor returns L0 bit for bit."""
+    a, l0 = inputs.integer_factor(300, 8)
+    ta = _t(torch_dev, a)
+    u = dc.DC_F32 if upd == "f32" else dc.DC_BF16
+    assert dc.potrf(rt, ta, 64, upd=u) == 0
+    assert np.array_equal(np.tril(ta.cpu().numpy()), l0)
+
+
+def test_mixed_factor_breakdown_reports_column(dc, rt, torch_dev):
+    a = inputs.spd_uniform(300, 4)
+    a[200, 200] = -1.0
+    ta = _t(torch_dev, a)
+    info = dc.potrf(rt, ta, 64, upd=dc.DC_F32)
+    _, info_ref = core.potrf_tiled(a, 64)
+    assert info == info_ref > 0

@@ -16,6 +16,7 @@ import numpy as np
 import pytest
 
 from oracle import core
+from bounds import assert_factor_elementwise
 from paper_1304_0878_amd import inputs
 
 pytestmark = pytest.mark.gpu
@@ -283,6 +284,7 @@ def test_potrf_matches_oracle(dc, rt, torch_dev, n, tile):
         assert eta <= 1e-13, eta
     cond = np.linalg.cond(a)
     assert np.linalg.norm(l - lr) / np.linalg.norm(lr) <= 8 * n * U * cond
+    assert_factor_elementwise(l, lr, a, cond)
 
 
 def test_potrf_ill_conditioned(dc, rt, torch_dev):

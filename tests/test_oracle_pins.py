@@ -468,6 +468,42 @@ def test_sampled_residual_and_residual_ld():
     assert np.array_equal(core.residual_f64(a, x0, bm), np.zeros((25, 2)))
 
 
+def test_sampled_residual_planted_perturbations():
+    """A = L0 L0^T + E with integer L0 and dyadic E: every sampled entry of
+    A - L L^T is E_ij exactly (both index orders), and a dyadic change d of
+    one factor entry L_{i0,p0} shows up exactly where it must: at
+    (i0, i0) as -(2 d L0[i0,p0] + d^2), at (i0, j) and (j, i0) for j >= p0 as
+    -d L0[j,p0], and nowhere else."""
+    n = 40
+    a, l0 = inputs.integer_factor(n, 5)
+    e = np.zeros_like(a)
+    pts = [(3, 1, 0.5), (17, 17, -0.25), (39, 0, 2.0), (25, 24, 1.75), (10, 9, -3.0)]
+    for i, j, v in pts:
+        e[i, j] = e[j, i] = v
+    rows = np.array([i for i, _, _ in pts] + [j for _, j, _ in pts] + [10, 39, 5])
+    cols = np.array([j for _, j, _ in pts] + [i for i, _, _ in pts] + [5, 38, 30])
+    got = core.sampled_residual(a + e, l0, rows, cols)
+    assert np.array_equal(got, np.array([e[r, c] for r, c in zip(rows, cols)]))
+
+    d, i0, p0 = 0.5, 20, 7
+    l = l0.copy()
+    l[i0, p0] += d
+    rows2 = np.array([20, 20, 30, 7, 20, 6, 20, 33])
+    cols2 = np.array([20, 7, 20, 20, 6, 20, 12, 31])
+    want = []
+    for r, c in zip(rows2, cols2):
+        if r == i0 and c == i0:
+            want.append(-(2 * d * l0[i0, p0] + d * d))
+        elif i0 in (r, c):
+            j = c if r == i0 else r
+            want.append(-d * l0[j, p0] if j >= p0 else 0.0)
+        else:
+            want.append(0.0)
+    got2 = core.sampled_residual(a, l, rows2, cols2)
+    assert np.array_equal(got2, np.array(want))
+    assert np.count_nonzero(want) == 5
+
+
 # -------------------------------------------------- mixed precision, IR
 
 def test_round_bf16_ties_to_even_against_torch():
