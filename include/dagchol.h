@@ -341,6 +341,25 @@ int dc_kernel_stats_get(dc_runtime *rt, dc_kernel_stats *out);
  * DC_BF16, and the inverse tiles) until dc_shutdown. */
 int dc_potrf(dc_runtime *rt, dc_handle A, int64_t tile, dc_dtype upd);
 
+/* dc_potrf_noalloc: for callers that cannot allocate memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation).  The
+ * FP64 factorisation of dc_potrf without any device or pinned-memory
+ * allocation (no hipMalloc, hipFree, hipHostMalloc or similar): the graph's
+ * device layout (task descriptors, work items, level counters, status words)
+ * is written to a fixed 16 MiB scratch array that the library keeps on every
+ * device it runs on until the process ends, staged through a fixed host area
+ * of the same size; both kernels of a level run on the runtime's stream.  The
+ * panel solves are substitution TRSM tasks (no inverse workspace), so the
+ * factor equals dc_potrf's up to rounding.  Host bookkeeping (handles, the
+ * task list) uses the C++ heap as every call does.  The counters the kernels
+ * start from are written by every call.  All calls on one device share its
+ * scratch array, and all calls share the staging area: calls that overlap
+ * race.  Errors: as dc_potrf; -ENOMEM (nothing runs) when the layout does not
+ * fit the scratch (n = 32768 with tile 512 fits; tiles far smaller than 128
+ * at large n do not); -EIO if the scratch's address could not be found when
+ * the runtime was created. */
+int dc_potrf_noalloc(dc_runtime *rt, dc_handle A, int64_t tile);
+
 /* dc_potrs: solves L L^T X = B in place in B (n x r, FP64) with the factor
  * in the lower triangle of L: forward sweep TRSM_L/GEMM_RHS_N, backward
  * sweep TRSM_LT/GEMM_RHS_T. */

@@ -17,7 +17,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdagchol.so")
 OBJ = os.path.join(ROOT, "_build")
-SOURCES = ["device.hip", "gemm_kernel.hip", "runtime.cpp", "highlevel.cpp", "ir.cpp", "serve.cpp"]
+SOURCES = ["device.hip", "gemm_kernel.hip", "noalloc.hip", "runtime.cpp", "highlevel.cpp", "ir.cpp",
+           "serve.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 COMPILE = [

@@ -129,6 +129,13 @@ extern "C++" int dcx_launch_queue_panel(const dcx::QueueArgs &args, int workers,
 // Launches the ready-queue workers of a GEMM class (dcq::CL_G64, CL_G32 or
 // CL_LOWP, args.cls) on `stream`.
 extern "C++" int dcx_launch_queue_gemm(const dcx::QueueArgs &args, int workers, void *stream);
+// The fixed scratch of the calls that allocate nothing: looks up the device
+// address of the scratch array on `device` (current) once; returns a
+// hipError_t value.
+extern "C++" int dcx_noalloc_setup(int device);
+// The scratch array's device address on `device`, the host staging area and
+// their size; 0, or -1 before dcx_noalloc_setup succeeded on that device.
+extern "C++" int dcx_noalloc_scratch(int device, void **dev, void **host, int64_t *bytes);
 // Workgroups per CU the queue panel kernel (instance inst) keeps resident
 // with lds_bytes of LDS.
 extern "C++" int dcx_queue_occupancy(size_t lds_bytes, int inst, int *blocks_per_cu);

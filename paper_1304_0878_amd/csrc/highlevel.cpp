@@ -11,6 +11,7 @@
 
 #include "../../include/dagchol.h"
 #include "runtime_internal.h"
+#include "exec_abi.h"
 
 namespace {
 
@@ -285,6 +286,41 @@ extern "C" int dc_potrf(dc_runtime *rt, dc_handle A, int64_t tile, dc_dtype upd)
     tw.close();
     const int e2 = dc_unregister(rt, wh);
     if (!e) e = e2;
+  }
+  return e;
+}
+
+extern "C" int dc_potrf_noalloc(dc_runtime *rt, dc_handle A, int64_t tile) {
+  if (!rt) return -EINVAL;
+  Handle *p = rt->get(A);
+  if (!p) return -ENOENT;
+  if (p->rows != p->cols || p->dtype != DC_F64 || tile < 1 || tile > dcx::MAX_TILE)
+    return -EINVAL;
+  if (p->partitioned) return -EBUSY;
+  if (rt->cfg.device < 0) return -ENODEV;
+  if (p->rows == 0) { p->info = 0; return 0; }
+  ExtArena arena;
+  if (dcx_noalloc_scratch(rt->cfg.device, &arena.dev, &arena.host, &arena.cap)) return -EIO;
+  // a graph flushed before this call runs on the runtime's own arena
+  TRY(dc_wait_all(rt));
+  int e;
+  {
+    Tiles t;
+    e = t.open(rt, A, tile);
+    if (!e) {
+      // panel solves by substitution: no inverse workspace
+      e = dcx_submit_potrf_tiles(rt, t.ids, t.tr, nullptr);
+      if (e) {
+        dcx_discard_pending(rt);
+      } else {
+        const bool timing = rt->ktiming;
+        rt->ktiming = false;   // timing events would be created on demand
+        rt->ext = &arena;
+        e = dc_wait_all(rt);
+        rt->ext = nullptr;
+        rt->ktiming = timing;
+      }
+    }
   }
   return e;
 }

@@ -143,6 +143,7 @@ extern "C" int dc_init(dc_runtime **out, const dc_config *cfg) {
     hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c.device);
     he = (hipError_t)dcx_level_setup();
     if (he == hipSuccess) he = (hipError_t)dcx_gemm_setup();
+    if (he == hipSuccess) he = (hipError_t)dcx_noalloc_setup(c.device);
     if (he != hipSuccess) { delete rt; return fail_hip(he, "hipFuncSetAttribute"); }
     he = hipStreamCreateWithFlags(&rt->side, hipStreamNonBlocking);
     if (he != hipSuccess) { delete rt; return fail_hip(he, "hipStreamCreate(side)"); }

@@ -116,6 +116,7 @@ _SIGS = {
     "dc_trace_get": (ctypes.c_int, [_P, _I64, _PI64, _PI64, _PI32, _PI32]),
     "dc_potrf": (ctypes.c_int, [_P, _H, _I64, ctypes.c_int]),
     "dc_potrs": (ctypes.c_int, [_P, _H, _H, _I64]),
+    "dc_potrf_noalloc": (ctypes.c_int, [_P, _H, _I64]),
     "dc_posv_ir": (ctypes.c_int, [_P, _H, _H, _H, _I64, ctypes.c_int, ctypes.c_double,
                                   ctypes.c_int, ctypes.POINTER(dc_ir_report)]),
     "dc_last_launch": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double), _PI64, _PI32]),
@@ -322,6 +323,9 @@ class Runtime:
     # -- high level
     def dc_potrf(self, a, tile, upd=DC_F64):
         _check(_lib.dc_potrf(self._ptr, a, tile, upd), "dc_potrf")
+
+    def dc_potrf_noalloc(self, a, tile):
+        _check(_lib.dc_potrf_noalloc(self._ptr, a, tile), "dc_potrf_noalloc")
 
     def dc_potrs(self, l, b, tile):
         _check(_lib.dc_potrs(self._ptr, l, b, tile), "dc_potrs")
