@@ -28,6 +28,7 @@ sys.path.insert(0, ROOT)
 
 FP64_PEAK_TFLOPS = 78.6   # MI355X dense FP64 matrix peak (published)
 FP32_PEAK_TFLOPS = 157.3  # MI355X dense FP32 matrix peak (published)
+HBM_PEAK_BPS = 8.0e12     # MI355X HBM3E bandwidth (published)
 METRIC = "Cholesky GFLOP/s + % MFMA peak (FP64 vs mixed@1e-10); solves/s with p50/p99"
 PROFILE = os.path.join(ROOT, "profiles", "dc_gemm_kernel_fp64_n32768.md")
 
@@ -79,10 +80,36 @@ def make_spd(torch, n, seed, kappa, dev):
     return a.contiguous(), lam, delta
 
 
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+_ONE_THREAD = r"""
+import sys, time
+sys.path.insert(0, {root!r})
+from oracle import core
+from paper_1304_0878_amd import inputs
+n = {n}
+a = inputs.spd_normal(n, 3, 1e-2)
+t = time.perf_counter()
+l, info = core.potrf_tiled(a, 256)
+print(time.perf_counter() - t, core.num_threads(), info)
+"""
+
+
 def cpu_baseline(target_s):
     """The plain C oracle (tiled FP64 factor in submission order) on a
-    bounded sample sized for about target_s seconds of host work."""
-    import numpy as np
+    bounded sample sized for about target_s seconds of host work, on every
+    host thread the process may use, and on one thread (a child process with
+    OMP_NUM_THREADS=1) on a smaller sample."""
+    import subprocess
     from oracle import core
     from paper_1304_0878_amd import inputs
     n0 = 2048
@@ -97,13 +124,131 @@ def cpu_baseline(target_s):
     l, info = core.potrf_tiled(a, 256)
     dt = time.perf_counter() - t
     assert info == 0
+    del a, l
+    one = None
+    try:
+        n1 = 2048
+        env = dict(os.environ, OMP_NUM_THREADS="1")
+        r = subprocess.run([sys.executable, "-c", _ONE_THREAD.format(root=ROOT, n=n1)],
+                           capture_output=True, text=True, timeout=300, env=env)
+        dt1, th1, info1 = r.stdout.split()
+        if int(info1) == 0 and int(th1) == 1:
+            one = {"value": round(flops_potrf(n1) / float(dt1) / 1e9, 2), "unit": "GFLOP/s",
+                   "cores": 1, "sample": f"same factorisation, n={n1}; {float(dt1):.1f} s"}
+    except (OSError, ValueError, subprocess.SubprocessError):
+        one = None
     return {"value": round(flops_potrf(n) / dt / 1e9, 2), "unit": "GFLOP/s",
-            "cores": core.num_threads(), "kind": "oracle",
+            "cores": core.num_threads(), "kind": "oracle", "cpu_model": _cpu_model(),
             "sample": f"tiled FP64 factorisation (tile 256) of one SPD matrix n={n}, "
-                      f"A = B B^T/n + 1e-2 I, B iid N(0,1); {dt:.1f} s"}
+                      f"A = B B^T/n + 1e-2 I, B iid N(0,1); {dt:.1f} s (the GPU figure "
+                      f"is n=32768: the oracle would need about "
+                      f"{flops_potrf(32768) / (flops_potrf(n) / dt) / 60:.0f} min)",
+            "one_thread": one}
 
 
-def leg_mixed(torch, dagchol, rt, stream, a0, l64, n, tile, seed):
+def _median(v):
+    v = sorted(v)
+    return v[len(v) // 2]
+
+
+def leg_small(torch, dagchol, dev, seed, reps=50):
+    """n = 512, tile 128 (4 x 4 tiles, 20 factor tasks): A = B B^T + n I, B
+    iid U[-1, 1], one right-hand side; latency of the FP64 factorisation and
+    of factorisation + solve, median of `reps` runs, each timed with HIP
+    events on the library's stream (A and b restored before each run,
+    outside the events)."""
+    import numpy as np
+    from paper_1304_0878_amd import inputs
+    n, tile = 512, 128
+    a0 = torch.from_numpy(inputs.spd_uniform(n, seed)).to(dev)
+    b0 = torch.from_numpy(inputs.rhs(n, seed + 1, 1)).to(dev)
+    stream = torch.cuda.Stream(device=dev)
+    rt = dagchol.Runtime(device=0, stream=stream)
+    a, b = torch.empty_like(a0), torch.empty_like(b0)
+    ha, hb = rt.register_tensor(a), rt.register_tensor(b)
+    fac, tot = [], []
+    for rep in range(reps + 3):
+        with torch.cuda.stream(stream):
+            a.copy_(a0)
+            b.copy_(b0)
+        torch.cuda.synchronize()
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        e0.record(stream)
+        rt.dc_potrf(ha, tile)
+        e1.record(stream)
+        rt.dc_potrs(ha, hb, tile)
+        e2.record(stream)
+        torch.cuda.synchronize()
+        if rep >= 3:
+            fac.append(e0.elapsed_time(e1) * 1e3)
+            tot.append(e0.elapsed_time(e2) * 1e3)
+    info = rt.dc_get_info(ha)
+    rt.dc_unregister(hb)
+    rt.dc_unregister(ha)
+    rt.close()
+    r = b0 - a0 @ b
+    berr = float(r.abs().max() / (a0.abs().sum(1).max() * b.abs().max() + b0.abs().max()))
+    return {"n": n, "tile": tile, "tasks": 20, "info": info, "reps": reps,
+            "factor_us_median": round(_median(fac), 1),
+            "factor_and_solve_us_median": round(_median(tot), 1),
+            "factor_gflops": round(flops_potrf(n) / (_median(fac) * 1e-6) / 1e9, 2),
+            "backward_error": berr}
+
+
+def leg_8192(torch, dagchol, dev, seed, reps=10):
+    """n = 8192, A = B B^T / n + 1e-2 I (B iid N(0, 1)), 16 right-hand sides:
+    the FP64 factorisation at tiles 256, 384 (ragged last tile) and 512,
+    median of `reps` runs, and the solve of the 16 right-hand sides."""
+    n, r = 8192, 16
+    g = torch.Generator(device=dev)
+    g.manual_seed(seed + 8192)
+    bm = torch.randn(n, n, dtype=torch.float64, device=dev, generator=g)
+    a0 = bm @ bm.T
+    del bm
+    a0.div_(n)
+    a0 = torch.tril(a0) + torch.tril(a0, -1).T
+    a0.diagonal().add_(1e-2)
+    b0 = torch.randn(n, r, dtype=torch.float64, device=dev, generator=g)
+    stream = torch.cuda.Stream(device=dev)
+    rt = dagchol.Runtime(device=0, stream=stream)
+    a, b = torch.empty_like(a0), torch.empty_like(b0)
+    ha, hb = rt.register_tensor(a), rt.register_tensor(b)
+    out = {"n": n, "rhs": r, "reps": reps}
+    for tile in (256, 384, 512):
+        fac, sol = [], []
+        for rep in range(reps + 1):
+            with torch.cuda.stream(stream):
+                a.copy_(a0)
+                b.copy_(b0)
+            torch.cuda.synchronize()
+            e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+            e0.record(stream)
+            rt.dc_potrf(ha, tile)
+            e1.record(stream)
+            rt.dc_potrs(ha, hb, tile)
+            e2.record(stream)
+            torch.cuda.synchronize()
+            if rep:
+                fac.append(e0.elapsed_time(e1))
+                sol.append(e1.elapsed_time(e2))
+        if rt.dc_get_info(ha):
+            raise RuntimeError("n = 8192 factorisation broke down")
+        res = b0 - a0 @ b
+        berr = float(res.abs().max() / (a0.abs().sum(1).max() * b.abs().max() + b0.abs().max()))
+        ms = _median(fac)
+        out[f"tile{tile}"] = {"factor_ms_median": round(ms, 3),
+                              "gflops": round(flops_potrf(n) / (ms * 1e-3) / 1e9, 1),
+                              "pct_fp64_peak": round(100 * flops_potrf(n) / (ms * 1e-3) / 1e12
+                                                     / FP64_PEAK_TFLOPS, 2),
+                              "solve_16rhs_ms_median": round(_median(sol), 3),
+                              "solution_backward_error": berr}
+    rt.dc_unregister(hb)
+    rt.dc_unregister(ha)
+    rt.close()
+    return out
+
+
+def leg_mixed(torch, dagchol, rt, stream, a0, l64, n, tile, seed, lam=None, delta=None):
     """Time to solution of one right-hand side at the main workload: the FP64
     factor (already timed) plus its solve, against dc_posv_ir with FP32 and
     BF16 updates (FP64 diagonal tiles, refinement to ||d|| <= 1e-12 ||x||).
@@ -133,30 +278,61 @@ def leg_mixed(torch, dagchol, rt, stream, a0, l64, n, tile, seed):
         torch.cuda.synchronize()
         return e0.elapsed_time(e1), out
 
-    x64 = b.clone()
-    solve_ms, _ = timed(lambda: dagchol.potrs(rt, l64, x64, tile))
-    res = {"fp64_solve_ms": round(solve_ms, 3), "fp64_backward_error": berr(x64)}
-    for name, code in (("f32", dagchol.DC_F32), ("bf16", dagchol.DC_BF16)):
-        x = torch.zeros_like(b)
-        ms, rep = timed(lambda: dagchol.posv_ir(rt, a0, b, x, tile, upd=code, tol=1e-12,
-                                                maxit=30))
+    def one_kappa():
+        x64 = b.clone()
         with torch.cuda.stream(stream):
-            dx = float((x - x64).abs().max() / x64.abs().max())
+            l64.copy_(a0)
         torch.cuda.synchronize()
-        res[name] = {"time_to_solution_ms": round(ms, 3),
-                     "fp64_equivalent_gflops": round(flops_potrf(n) / (ms * 1e-3) / 1e9, 1),
-                     "factor_ms": round(rep["factor_ms"], 3), "refine_ms": round(rep["refine_ms"], 3),
-                     "iterations": rep["iterations"], "converged": rep["converged"],
-                     "final_update_precision": {0: "f64", 1: "f32", 2: "bf16"}[rep["final_prec"]],
-                     "fallbacks": rep["fallbacks"], "backward_error": berr(x),
-                     "rel_diff_to_fp64_solution": dx}
-    return res
+        fac_ms, _ = timed(lambda: dagchol.potrf(rt, l64, tile))
+        solve_ms, _ = timed(lambda: dagchol.potrs(rt, l64, x64, tile))
+        res = {"fp64_factor_ms": round(fac_ms, 3), "fp64_solve_ms": round(solve_ms, 3),
+               "fp64_time_to_solution_ms": round(fac_ms + solve_ms, 3),
+               "fp64_backward_error": berr(x64)}
+        for name, code in (("f32", dagchol.DC_F32), ("bf16", dagchol.DC_BF16)):
+            x = torch.zeros_like(b)
+            ms, rep = timed(lambda: dagchol.posv_ir(rt, a0, b, x, tile, upd=code, tol=1e-12,
+                                                    maxit=30))
+            with torch.cuda.stream(stream):
+                dx = float((x - x64).abs().max() / x64.abs().max())
+            torch.cuda.synchronize()
+            res[name] = {"time_to_solution_ms": round(ms, 3),
+                         "fp64_equivalent_gflops": round(flops_potrf(n) / (ms * 1e-3) / 1e9, 1),
+                         "factor_ms": round(rep["factor_ms"], 3),
+                         "refine_ms": round(rep["refine_ms"], 3),
+                         "iterations": rep["iterations"], "converged": rep["converged"],
+                         "final_update_precision": {0: "f64", 1: "f32", 2: "bf16"}[rep["final_prec"]],
+                         "fallbacks": rep["fallbacks"], "backward_error": berr(x),
+                         "rel_diff_to_fp64_solution": dx}
+        return res
+
+    out = {}
+    shift0 = 0.0
+    for kappa in (1e2, 1e4, 1e6):
+        # the matrix of the main workload has cond ~1e2; the others move its
+        # diagonal shift from lam/(1e2 - 1) to lam/(kappa - 1)
+        shift = 0.0 if lam is None else lam / (kappa - 1.0) - delta
+        with torch.cuda.stream(stream):
+            a0.diagonal().add_(shift - shift0)
+        torch.cuda.synchronize()
+        shift0 = shift
+        out[f"cond{kappa:.0e}"] = one_kappa()
+        if lam is None:
+            break
+    with torch.cuda.stream(stream):
+        a0.diagonal().add_(-shift0)
+    torch.cuda.synchronize()
+    return out
 
 
 def leg_batched(torch, dagchol, dev, seed, count, reps):
     """One graph factoring and solving `count` SPD matrices (n uniform in
     [16, 512], 1-4 right-hand sides, A = B B^T + n I with B uniform in
-    [-1, 1]) in FP64; tiles from the measured tuning cache when present."""
+    [-1, 1]), once with the matrices in FP64 and once in FP32 (the factor
+    stored in FP32, FP64 arithmetic; right-hand sides FP64); tiles from the
+    measured tuning cache when present.  Reports the median host call time,
+    the host's graph build inside it, and the fraction of the sum of the
+    per-matrix roofline floors max(flop / MFMA peak, compulsory bytes / HBM
+    bandwidth) at the published peaks."""
     import numpy as np
     from paper_1304_0878_amd import tune
     rng = np.random.default_rng(seed)
@@ -166,65 +342,86 @@ def leg_batched(torch, dagchol, dev, seed, count, reps):
     tiles = tune.tiles_for(ns, cache) if cache else [0 if v <= 128 else 128 for v in ns]
     g = torch.Generator(device=dev)
     g.manual_seed(seed)
-    mats, rhs, keep_a, keep_b = [], [], [], []
+    keep_a, keep_b = [], []
     for n_i, r_i in zip(ns, rs):
         bm = torch.rand(n_i, n_i, dtype=torch.float64, device=dev, generator=g) * 2 - 1
         a_i = bm @ bm.T
         a_i.diagonal().add_(n_i)
         keep_a.append(a_i)
         keep_b.append(torch.randn(n_i, r_i, dtype=torch.float64, device=dev, generator=g))
-        mats.append(torch.empty_like(a_i))
-        rhs.append(torch.empty_like(keep_b[-1]))
     torch.cuda.synchronize()
-    rt = dagchol.Runtime(device=0)
-    ha = [rt.register_tensor(m) for m in mats]
-    hb = [rt.register_tensor(v) for v in rhs]
-    times = []
-    for rep in range(reps + 1):
-        for m, k in zip(mats, keep_a):
-            m.copy_(k)
-        for v, k in zip(rhs, keep_b):
-            v.copy_(k)
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        infos = rt.dc_potrf_batched(ha, hb, tiles)
-        torch.cuda.synchronize()
-        if rep:
-            times.append(time.perf_counter() - t)
-        if any(infos):
-            raise RuntimeError("batched factorisation broke down")
-    for h in hb + ha:
-        rt.dc_unregister(h)
-    rt.close()
-    # accuracy of a sample: normwise backward error of the solutions
-    worst = 0.0
-    for i in range(0, count, max(1, count // 64)):
-        r = keep_b[i] - keep_a[i] @ rhs[i]
-        worst = max(worst, float(r.abs().max() / (keep_a[i].abs().sum(1).max() * rhs[i].abs().max()
-                                                  + keep_b[i].abs().max())))
-    ms = sorted(times)[len(times) // 2] * 1e3
     flop = sum(flops_potrf(v) + 2.0 * v * v * r for v, r in zip(ns, rs))
-    return {"matrices": count, "median_ms": round(ms, 3),
-            "matrices_per_s": round(count / (ms * 1e-3), 1),
-            "gflops": round(flop / (ms * 1e-3) / 1e9, 1),
-            "tiles": "tuning cache" if cache else "rule: whole matrix up to 128, else 128",
-            "worst_backward_error_sample": worst,
-            "note": "FP64; one host call = graph build + upload + all level launches + wait"}
+
+    def floor_ms(esize, peak_tflops):
+        t = 0.0
+        for v, r in zip(ns, rs):
+            f = flops_potrf(v) + 2.0 * v * v * r
+            b = 2.0 * v * (v + 1) / 2 * esize + 2.0 * v * r * 8
+            t += max(f / (peak_tflops * 1e12), b / HBM_PEAK_BPS)
+        return t * 1e3
+
+    out = {"matrices": count, "tiles": "tuning cache" if cache
+           else "rule: whole matrix up to 128, else 128"}
+    for name, dt, esize, peak in (("fp64", torch.float64, 8, FP64_PEAK_TFLOPS),
+                                  ("fp32", torch.float32, 4, FP32_PEAK_TFLOPS)):
+        mats = [torch.empty(k.shape, dtype=dt, device=dev) for k in keep_a]
+        rhs = [torch.empty_like(k) for k in keep_b]
+        tl = tiles if name == "fp64" else [0] * count
+        rt = dagchol.Runtime(device=0)
+        ha = [rt.register_tensor(m) for m in mats]
+        hb = [rt.register_tensor(v) for v in rhs]
+        times, builds = [], []
+        for rep in range(reps + 1):
+            for m, k in zip(mats, keep_a):
+                m.copy_(k)
+            for v, k in zip(rhs, keep_b):
+                v.copy_(k)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            infos = rt.dc_potrf_batched(ha, hb, tl)
+            torch.cuda.synchronize()
+            if rep:
+                times.append(time.perf_counter() - t)
+                builds.append(rt.dc_last_launch()["build_ms"])
+            if any(infos):
+                raise RuntimeError("batched factorisation broke down")
+        for h in hb + ha:
+            rt.dc_unregister(h)
+        rt.close()
+        worst = 0.0
+        for i in range(0, count, max(1, count // 64)):
+            r = keep_b[i] - keep_a[i] @ rhs[i]
+            worst = max(worst, float(r.abs().max() / (keep_a[i].abs().sum(1).max()
+                                                      * rhs[i].abs().max() + keep_b[i].abs().max())))
+        ms = _median(times) * 1e3
+        fl = floor_ms(esize, peak)
+        out[name] = {"median_ms": round(ms, 3), "host_graph_build_ms": round(_median(builds), 3),
+                     "matrices_per_s": round(count / (ms * 1e-3), 1),
+                     "gflops": round(flop / (ms * 1e-3) / 1e9, 1),
+                     "roofline_floor_ms": round(fl, 3), "frac_of_floor": round(fl / ms, 4),
+                     "worst_backward_error_sample": worst}
+        del mats, rhs
+    out["note"] = ("one host call = graph build + upload + all level launches + wait; "
+                   "FP32: one POTRF task per matrix")
+    return out
 
 
-def leg_serving(torch, dagchol, dev, seed, nreq, nmax):
+def leg_serving(torch, dagchol, dev, seed, nreq, nmax, npool=96, sweep=(0.5, 0.9, 1.2),
+                mixed_min=0):
     """Open-loop serving: requests (n log-uniform in [32, nmax], 1-8
-    right-hand sides, cond <= 1e2..1e6) drawn from a device-resident pool of
-    matrices.  The saturated throughput of the FP64 path is measured first
-    (all requests at t = 0); both paths then serve a Poisson arrival stream
-    at 0.7 times that rate.  Latency = completion - arrival."""
+    right-hand sides, cond 10^U(2, 6)) drawn from a device-resident pool of
+    `npool` matrices generated before the timed runs.  The saturated
+    throughput mu64 of the FP64 path is measured first (all requests at
+    t = 0), then the mixed path's; both paths then serve the same Poisson
+    arrival stream at lambda = f * mu64 for each f of `sweep`.  Latency =
+    completion - arrival; p50/p99 by nearest rank over all requests."""
     import math as _m
     import numpy as np
     rng = np.random.default_rng(seed)
     pool = []
     g = torch.Generator(device=dev)
     g.manual_seed(seed + 7)
-    for i in range(24):
+    for i in range(npool):
         n_i = int(round(_m.exp(rng.uniform(_m.log(32), _m.log(nmax)))))
         kappa = 10.0 ** rng.uniform(2, 6)
         a_i, _, _ = make_spd(torch, n_i, seed * 100 + i, kappa, dev)
@@ -240,7 +437,7 @@ def leg_serving(torch, dagchol, dev, seed, nreq, nmax):
 
     def serve(upd, arrivals):
         srv = dagchol.Server(device=0, slots=8, pool_bytes=96 << 30, tile=256, upd=upd,
-                             tol=1e-12, maxit=30)
+                             tol=1e-12, maxit=30, mixed_min=mixed_min)
         t0 = srv.now()
         done, i = [], 0
         while len(done) < nreq:
@@ -255,31 +452,37 @@ def leg_serving(torch, dagchol, dev, seed, nreq, nmax):
         lat = sorted(d["completed"] - d["arrival"] for d in done)
         span = max(d["completed"] for d in done) - (t0 + arrivals[0])
         bad = [d for d in done if d["status"] != 0 or not d["converged"]]
+        rank = lambda q: lat[max(0, min(len(lat) - 1, int(math.ceil(q * len(lat))) - 1))]
+        worst = 0.0
+        for a_i, b_i, x_i in reqs[:: max(1, nreq // 32)]:
+            r = b_i - a_i @ x_i
+            worst = max(worst, float(r.abs().max() / (a_i.abs().sum(1).max() * x_i.abs().max()
+                                                      + b_i.abs().max())))
         return {"solves_per_s": round(nreq / span, 2),
-                "p50_ms": round(lat[len(lat) // 2] * 1e3, 2),
-                "p99_ms": round(lat[min(len(lat) - 1, int(0.99 * len(lat)))] * 1e3, 2),
+                "p50_ms": round(rank(0.50) * 1e3, 2),
+                "p99_ms": round(rank(0.99) * 1e3, 2),
                 "unconverged_or_failed": len(bad),
                 "restarts": sum(d["restarts"] for d in done),
-                "gflops": round(flop / span / 1e9, 1)}
+                "gflops": round(flop / span / 1e9, 1),
+                "worst_backward_error_sample": worst}
 
     zero = [0.0] * nreq
     sat64 = serve(dagchol.DC_F64, zero)
     sat32 = serve(dagchol.DC_F32, zero)
-    lam = 0.7 * sat64["solves_per_s"]
-    gaps = rng.exponential(1.0 / lam, nreq)
-    arr = list(np.cumsum(gaps) - gaps[0])
-    open64 = serve(dagchol.DC_F64, arr)
-    open32 = serve(dagchol.DC_F32, arr)
-    worst = 0.0
-    for a_i, b_i, x_i in reqs[:: max(1, nreq // 32)]:
-        r = b_i - a_i @ x_i
-        worst = max(worst, float(r.abs().max() / (a_i.abs().sum(1).max() * x_i.abs().max()
-                                                  + b_i.abs().max())))
+    mu = sat64["solves_per_s"]
+    gaps = rng.exponential(1.0, nreq)
+    unit = list(np.cumsum(gaps) - gaps[0])      # arrivals of a rate-1 Poisson stream
+    opened = {}
+    for f in sweep:
+        arr = [t / (f * mu) for t in unit]
+        opened[f"lambda_{f:g}_mu64"] = {"arrival_rate_per_s": round(f * mu, 2),
+                                        "fp64": serve(dagchol.DC_F64, arr),
+                                        "mixed_f32": serve(dagchol.DC_F32, arr)}
     return {"requests": nreq, "n_range": [32, nmax], "pool_matrices": len(pool),
-            "arrival_rate_per_s": round(lam, 2),
+            "mixed_path": f"FP32 updates for orders >= {mixed_min}, FP64 updates below",
+            "mu64_solves_per_s": mu,
             "saturated": {"fp64": sat64, "mixed_f32": sat32},
-            "open_loop": {"fp64": open64, "mixed_f32": open32},
-            "worst_backward_error_sample": worst}
+            "open_loop": opened}
 
 
 def main():
@@ -293,11 +496,13 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--legs", default="mixed,batched,serving",
+    ap.add_argument("--legs", default="mixed,small,n8192,batched,serving",
                     help="extra measurements after the FP64 factorisation (comma list, or none)")
     ap.add_argument("--batch-count", type=int, default=10000)
-    ap.add_argument("--serve-requests", type=int, default=200)
+    ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-nmax", type=int, default=16384)
+    ap.add_argument("--mixed-min", type=int, default=0,
+                    help="serving: orders below this use FP64 updates on the mixed path")
 
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -357,17 +562,22 @@ def main():
     legs = [v for v in args.legs.split(",") if v and v != "none"]
     extra = {}
     if "mixed" in legs:
-        extra["mixed_precision"] = leg_mixed(torch, dagchol, rt, stream, a0, a, n, tile, args.seed)
+        extra["mixed_precision"] = leg_mixed(torch, dagchol, rt, stream, a0, a, n, tile,
+                                             args.seed, lam, delta)
     rt.close()
     del a
     torch.cuda.empty_cache()
+    if "small" in legs:
+        extra["n512_latency"] = leg_small(torch, dagchol, dev, args.seed)
+    if "n8192" in legs:
+        extra["n8192"] = leg_8192(torch, dagchol, dev, args.seed)
     if "batched" in legs:
         extra["batched"] = leg_batched(torch, dagchol, dev, args.seed, args.batch_count, 3)
     if "serving" in legs:
         del a0
         torch.cuda.empty_cache()
         extra["serving"] = leg_serving(torch, dagchol, dev, args.seed, args.serve_requests,
-                                       args.serve_nmax)
+                                       args.serve_nmax, mixed_min=args.mixed_min)
 
     # roofline of the dominant kernel (GEMM/SYRK updates): its algorithmic
     # flops per launch over its average launch duration

@@ -81,8 +81,10 @@ typedef enum { DC_F64 = 0, DC_F32 = 1, DC_BF16 = 2 } dc_dtype;
 /*
  * Task kinds and their buffer signatures (handles in this order):
  *   DC_POTRF      (D:RW)            D = L L^T in place, lower, one diagonal
- *                                   tile; scalar: int64 global row offset of
- *                                   D (for the info column), optional.
+ *                                   tile (FP64, or FP32 computed in FP64 and
+ *                                   rounded on store); scalar: int64 global
+ *                                   row offset of D (for the info column),
+ *                                   optional.
  *   DC_TRSM       (L:R, X:RW)       X <- X L^{-T}, L lower non-unit.
  *   DC_SYRK       (X:R, C:RW)       lower(C) <- lower(C) - X X^T.
  *   DC_GEMM       (X:R, Y:R, C:RW)  C <- C - X Y^T.
@@ -122,7 +124,7 @@ typedef enum { DC_F64 = 0, DC_F32 = 1, DC_BF16 = 2 } dc_dtype;
  *                                   L, W, S and D, order 16..512); both fall
  *                                   back to substitution like DC_TRSM_INV.
  * Precisions (the dtypes of the handles select the kernel):
- *   POTRF: FP64.  TRSM: L FP64, X FP64 or FP32 (FP64 arithmetic, FP32 tiles
+ *   POTRF: FP64 or FP32 storage, FP64 arithmetic.  TRSM: L FP64, X FP64 or FP32 (FP64 arithmetic, FP32 tiles
  *   rounded on store).  SYRK/GEMM: FP64 inputs update FP64 tiles with FP64
  *   MFMA; FP32 or BF16 inputs (both operands of one dtype) multiply with
  *   FP32 accumulation and the product is subtracted from an FP32 or FP64
@@ -395,9 +397,12 @@ int dc_posv_ir(dc_runtime *rt, dc_handle A, dc_handle B, dc_handle X,
                dc_ir_report *rep);
 
 /* Batched factorisation and solve: factors each of the count SPD matrices
- * A[i] (FP64, lower triangle, in place) with tile size tiles[i] (0: the
- * matrix order, i.e. one POTRF task) and, where B != NULL and B[i] != 0,
- * solves A[i] X = B[i] in place in B[i].  All tasks of all matrices form one
+ * A[i] (lower triangle, in place) with tile size tiles[i] (0: the matrix
+ * order, i.e. one POTRF task) and, where B != NULL and B[i] != 0, solves
+ * A[i] X = B[i] in place in B[i] (B FP64).  A[i] is FP64, or FP32 factored as
+ * one tile (tiles[i] 0 or >= its order; FP64 arithmetic, the factor rounded
+ * to FP32, the solve in FP64 arithmetic on the FP32 factor); FP64 and FP32
+ * matrices may be mixed in one call.  All tasks of all matrices form one
  * graph, run by one flush of the executor.  info_out (optional) receives
  * each matrix's status (0 or the 1-based breakdown column).  Errors as for
  * dc_potrf; on an error no task runs. */
@@ -431,6 +436,11 @@ typedef struct {
                           factored as a single tile, larger ones with
                           `tile`; default 512, 0: every request uses
                           `tile` */
+  int64_t mixed_min;   /* with upd FP32 or BF16: requests of order below
+                          mixed_min use FP64 updates (their factorisation
+                          costs less than the refinement steps the
+                          low-precision factor needs); default 0: every
+                          request uses upd */
 } dc_server_config;
 
 typedef struct {

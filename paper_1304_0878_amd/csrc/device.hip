@@ -494,9 +494,13 @@ __device__ __forceinline__ void run_trsm_inv(const TaskDesc &d, int unit, double
 // wave, and publishes it; after one barrier every thread finishes the rows
 // below the block by substitution.  Returns 0 or the 1-based local column of
 // the first non-positive pivot.
+// TS: the storage type of the tile (double, or float for an FP32 factor:
+// every value is widened on load, the arithmetic is FP64, and each store
+// rounds to FP32).
+template <typename TS>
 __device__ __forceinline__ int run_potrf(const TaskDesc &d, double *lds) {
   const int nb = d.m;
-  gdouble *D = (gdouble *)d.c;
+  gptr<TS> D = (gptr<TS>)d.c;
   const int64_t ldd = d.ldc;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -519,12 +523,12 @@ __device__ __forceinline__ int run_potrf(const TaskDesc &d, double *lds) {
     const int wj = min(PANEL, nb - c0);
     const int nrows = nb - c0;
     if (c0 > 0) {
-      stage16<double>(Bp, BS, D + (int64_t)c0 * ldd, ldd, wj, c0);
+      stage16<TS>(Bp, BS, D + (int64_t)c0 * ldd, ldd, wj, c0);
       __syncthreads();
       const int ngroups = (nrows + 15) / 16;
       double acc[GQ][4];
       double an[GQ][4];
-      const gdouble *ap[GQ];
+      gptr<const TS> ap[GQ];
       bool aok[GQ];
 #pragma unroll
       for (int q = 0; q < GQ; ++q) {
@@ -571,8 +575,8 @@ __device__ __forceinline__ int run_potrf(const TaskDesc &d, double *lds) {
           for (int s = 0; s < 4; ++s) {
             const int col = 4 * ((blk + s) & 3) + n4;
             if (row < nb && col < wj && c0 + col <= row) {
-              gdouble *p = D + (int64_t)row * ldd + c0 + col;
-              *p = *p - acc[q][s];
+              gptr<TS> p = D + (int64_t)row * ldd + c0 + col;
+              *p = (TS)((double)*p - acc[q][s]);
             }
           }
         }
@@ -590,7 +594,7 @@ __device__ __forceinline__ int run_potrf(const TaskDesc &d, double *lds) {
       const int row = c0 + tid + NT * q;
 #pragma unroll
       for (int j = 0; j < PANEL; ++j)
-        v[q][j] = (row < nb && j < wj && c0 + j <= row) ? D[(int64_t)row * ldd + c0 + j] : 0.0;
+        v[q][j] = (row < nb && j < wj && c0 + j <= row) ? (double)D[(int64_t)row * ldd + c0 + j] : 0.0;
     }
     if (w == 0) {
       int f = 0;
@@ -647,7 +651,7 @@ __device__ __forceinline__ int run_potrf(const TaskDesc &d, double *lds) {
         const int row = c0 + tid + NT * q;
 #pragma unroll
         for (int j = 0; j < PANEL; ++j)
-          if (row < nb && j < wj && c0 + j <= row) D[(int64_t)row * ldd + c0 + j] = v[q][j];
+          if (row < nb && j < wj && c0 + j <= row) D[(int64_t)row * ldd + c0 + j] = (TS)v[q][j];
       }
     }
     __syncthreads();
@@ -1275,7 +1279,7 @@ __device__ __forceinline__ void run_panel_unit(const TaskDesc &d, int u, double 
     case K_TRTRI: trsm_core<true>(d, u, lds, (const gdouble *)d.a, d.lda); break;
     case K_TRSM_INV: case K_TRSM_INV_CAST: run_trsm_inv(d, u, lds); break;
     case K_POTRF: {
-      const int bad = run_potrf(d, lds);
+      const int bad = d.tc == T_F32 ? run_potrf<float>(d, lds) : run_potrf<double>(d, lds);
       if (bad && threadIdx.x == 0 && d.matrix >= 0) {
         info[d.matrix] = d.row0 + bad;
         failed[d.matrix] = 1;

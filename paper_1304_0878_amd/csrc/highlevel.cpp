@@ -399,8 +399,10 @@ extern "C" int dc_potrf_batched(dc_runtime *rt, int64_t count, const dc_handle *
     Handle *p = rt->get(A[i]);
     if (!p) return -ENOENT;
     const int64_t tile = tiles[i] > 0 ? std::min(tiles[i], p->rows) : p->rows;
-    if (p->rows != p->cols || p->dtype != DC_F64 || tiles[i] < 0 ||
-        (p->rows > 0 && (tile < 1 || tile > dcx::MAX_TILE)))
+    // FP32 matrices are factored as one tile (POTRF on FP32 storage)
+    if (p->rows != p->cols || (p->dtype != DC_F64 && p->dtype != DC_F32) || tiles[i] < 0 ||
+        (p->rows > 0 && (tile < 1 || tile > dcx::MAX_TILE)) ||
+        (p->dtype == DC_F32 && tile < p->rows))
       return -EINVAL;
     if (p->partitioned) return -EBUSY;
     if (B && B[i]) {

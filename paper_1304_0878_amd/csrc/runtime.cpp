@@ -158,11 +158,11 @@ extern "C" int dc_init(dc_runtime **out, const dc_config *cfg) {
 }
 
 static void free_device(dc_runtime *rt) {
-  if (rt->arena_dev) hipFree(rt->arena_dev);
-  if (rt->arena_host) hipHostFree(rt->arena_host);
-  rt->arena_dev = nullptr;
-  rt->arena_host = nullptr;
-  rt->arena_cap = 0;
+  for (Arena &a : rt->arenas) {
+    if (a.dev) hipFree(a.dev);
+    if (a.host) hipHostFree(a.host);
+  }
+  rt->arenas.clear();
 }
 
 extern "C" int dc_shutdown(dc_runtime *rt) {
@@ -173,8 +173,8 @@ extern "C" int dc_shutdown(dc_runtime *rt) {
     free_device(rt);
     if (rt->inv_ws) hipFree(rt->inv_ws);
     if (rt->mix_ws) hipFree(rt->mix_ws);
-    for (hipEvent_t e : rt->events) hipEventDestroy(e);
-    for (hipEvent_t e : rt->tevents) hipEventDestroy(e);
+    for (hipEvent_t e : rt->ev_pool) hipEventDestroy(e);
+    for (hipEvent_t e : rt->tev_pool) hipEventDestroy(e);
     if (rt->side) hipStreamDestroy(rt->side);
     if (rt->side2) hipStreamDestroy(rt->side2);
     if (rt->side3) hipStreamDestroy(rt->side3);
@@ -234,7 +234,7 @@ extern "C" int dc_handle_lookup(dc_runtime *rt, const void *ptr, dc_handle *out)
 static bool has_pending(dc_runtime *rt, dc_handle h, bool inflight) {
   Handle *p = rt->get(h);
   if (!p) return false;
-  if (p->pending || (inflight && rt->inflight && p->inflight_ref)) return true;
+  if (p->pending || (inflight && p->inflight_ref > 0)) return true;
   for (dc_handle t : p->tiles)
     if (has_pending(rt, t, inflight)) return true;
   return false;
@@ -410,7 +410,10 @@ static int make_desc(dc_runtime *rt, dc_kind kind, const std::vector<Handle *> &
   switch (kind) {
     case DC_POTRF: {
       Handle *D = H[0];
-      if (!f64(D) || D->rows != D->cols || D->rows > MAX_TILE) return -EINVAL;
+      // FP64 tile, or an FP32 tile factored in FP64 arithmetic and rounded
+      // to FP32 on store
+      if ((!f64(D) && D->dtype != DC_F32) || D->rows != D->cols || D->rows > MAX_TILE)
+        return -EINVAL;
       d.m = (int)D->rows;
       d.c = D->ptr; d.ldc = D->ld; d.tc = D->dtype;
       int64_t row0 = D->row_off;
@@ -694,23 +697,68 @@ extern "C" int dc_trace_get(dc_runtime *rt, int64_t t, int64_t *start_ns, int64_
 
 static int hip_err(hipError_t e) { return e == hipSuccess ? 0 : -EIO; }
 
-// Waits for the launched graph and copies back its status and info words.
-static int finalize(dc_runtime *rt) {
-  if (!rt->inflight) return 0;
-  rt->inflight = false;
-  Inflight &f = rt->fl;
+// Events from the runtime's pools (created on first need, returned when the
+// graph that used them is collected).
+static hipEvent_t take_event(dc_runtime *rt, bool timing) {
+  std::vector<hipEvent_t> &pool = timing ? rt->tev_pool : rt->ev_pool;
+  if (!pool.empty()) {
+    hipEvent_t e = pool.back();
+    pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  const hipError_t he =
+      timing ? hipEventCreate(&e) : hipEventCreateWithFlags(&e, hipEventDisableTiming);
+  return he == hipSuccess ? e : nullptr;
+}
+
+// An arena of at least `bytes` that no graph in flight uses.  There is always
+// one to take or grow: a flush first collects graphs until fewer than
+// MAX_INFLIGHT are in flight, and each holds one arena.
+static int acquire_arena(dc_runtime *rt, int64_t bytes, int *out) {
+  int pick = -1;
+  for (size_t i = 0; i < rt->arenas.size(); ++i) {
+    const Arena &a = rt->arenas[i];
+    if (a.busy) continue;
+    if (a.cap >= bytes) { pick = (int)i; break; }
+    if (pick < 0) pick = (int)i;
+  }
+  if (pick < 0) {
+    if (rt->arenas.size() >= MAX_INFLIGHT) return -ENOMEM;
+    rt->arenas.push_back(Arena());
+    pick = (int)rt->arenas.size() - 1;
+  }
+  Arena &a = rt->arenas[pick];
+  if (a.cap < bytes) {
+    if (a.dev) hipFree(a.dev);
+    if (a.host) hipHostFree(a.host);
+    a = Arena();
+    const int64_t cap = align_up(bytes + bytes / 4, 1 << 20);
+    if (hipMalloc(&a.dev, cap) != hipSuccess) { a.dev = nullptr; return -ENOMEM; }
+    if (hipHostMalloc(&a.host, cap, hipHostMallocDefault) != hipSuccess) {
+      hipFree(a.dev);
+      a = Arena();
+      return -ENOMEM;
+    }
+    a.cap = cap;
+  }
+  a.busy = true;
+  *out = pick;
+  return 0;
+}
+
+// Collects one finished graph: copies back its status and info words (and
+// trace), adds its timed launches to the kernel statistics, and returns its
+// arena, events and handle references.
+static int retire(dc_runtime *rt, Inflight &f) {
   for (dc_handle h : f.handles)
-    if (Handle *p = rt->get(h)) p->inflight_ref = false;
-  f.handles.clear();
-  hipError_t e = hipStreamSynchronize(rt->stream);
-  if (e != hipSuccess) return fail_hip(e, "hipStreamSynchronize");
-  // status, info and failed words live at the end of the arena
+    if (Handle *p = rt->get(h)) p->inflight_ref -= 1;
+  int status = 0;
   std::vector<char> tail(f.tail_bytes);
-  e = hipMemcpy(tail.data(), (char *)f.arena_dev + f.tail_off, f.tail_bytes,
-                hipMemcpyDeviceToHost);
-  if (e != hipSuccess) return -EIO;
-  int32_t status = 0;
-  if (f.status_off >= 0) {
+  hipError_t e = hipMemcpy(tail.data(), (char *)f.arena_dev + f.tail_off, f.tail_bytes,
+                           hipMemcpyDeviceToHost);
+  if (e != hipSuccess) status = fail_hip(e, "hipMemcpy(graph status)");
+  if (!status && f.status_off >= 0) {
     int32_t st = 0;
     memcpy(&st, tail.data() + (f.status_off - f.tail_off), 4);
     if (st) {
@@ -718,33 +766,87 @@ static int finalize(dc_runtime *rt) {
       status = -ETIMEDOUT;
     }
   }
-  for (size_t s = 0; s < f.slot_roots.size(); ++s) {
-    if (!f.slot_factor[s]) continue;   // only a factorisation sets the status
-    int64_t info;
-    memcpy(&info, tail.data() + (f.info_off - f.tail_off) + s * 8, 8);
-    Handle &h = rt->handles[f.slot_roots[s] - 1];
-    h.info = info;
-  }
+  if (!status)
+    for (size_t s = 0; s < f.slot_roots.size(); ++s) {
+      if (!f.slot_factor[s]) continue;   // only a factorisation sets the status
+      int64_t info;
+      memcpy(&info, tail.data() + (f.info_off - f.tail_off) + s * 8, 8);
+      Handle *h = rt->get(f.slot_roots[s]);
+      if (h) h->info = info;
+    }
   for (const Inflight::Timed &t : f.timed) {
     float ms = 0.0f;
-    if (hipEventElapsedTime(&ms, rt->tevents[t.b], rt->tevents[t.e]) != hipSuccess) return -EIO;
+    if (!status && hipEventElapsedTime(&ms, t.b, t.e) != hipSuccess) status = -EIO;
     dc_kernel_stat &k = t.cls ? rt->kstats.gemm : rt->kstats.panel;
     k.launches += 1;
     k.ms += ms;
     k.flops += t.flops;
     k.bytes += t.bytes;
+    rt->tev_pool.push_back(t.b);
+    rt->tev_pool.push_back(t.e);
   }
-  f.timed.clear();
-  if (f.trace_off) {
+  if (!status && f.trace_off) {
     rt->trace_host.resize(3 * (size_t)f.ntasks);
     e = hipMemcpy(rt->trace_host.data(), (char *)f.arena_dev + f.trace_off,
                   rt->trace_host.size() * 8, hipMemcpyDeviceToHost);
-    if (e != hipSuccess) return -EIO;
-    rt->trace_t0 = INT64_MAX;
-    for (int64_t t = 0; t < f.ntasks; ++t) rt->trace_t0 = std::min(rt->trace_t0, rt->trace_host[3 * t]);
-    rt->trace_kind = f.kinds;
+    if (e != hipSuccess) {
+      status = fail_hip(e, "hipMemcpy(trace)");
+    } else {
+      rt->trace_t0 = INT64_MAX;
+      for (int64_t t = 0; t < f.ntasks; ++t)
+        rt->trace_t0 = std::min(rt->trace_t0, rt->trace_host[3 * t]);
+      rt->trace_kind = f.kinds;
+    }
   }
+  for (hipEvent_t ev : f.evs) rt->ev_pool.push_back(ev);
+  if (f.done) rt->ev_pool.push_back(f.done);
+  if (f.arena >= 0) rt->arenas[f.arena].busy = false;
   return status;
+}
+
+// Collects flushed graphs in order: waits until at most `keep` remain in
+// flight, then also collects the ones that have already finished.  Returns
+// the first error met.
+static int collect(dc_runtime *rt, size_t keep) {
+  int err = 0;
+  while (!rt->flq.empty()) {
+    Inflight &f = rt->flq.front();
+    if (!f.done) {
+      const hipError_t e = hipStreamSynchronize(rt->stream);
+      if (e != hipSuccess && !err) err = fail_hip(e, "hipStreamSynchronize");
+    } else if (rt->flq.size() > keep) {
+      const hipError_t e = hipEventSynchronize(f.done);
+      if (e != hipSuccess && !err) err = fail_hip(e, "hipEventSynchronize");
+    } else {
+      const hipError_t q = hipEventQuery(f.done);
+      if (q == hipErrorNotReady) break;
+      if (q != hipSuccess && !err) err = fail_hip(q, "hipEventQuery");
+    }
+    const int e2 = retire(rt, f);
+    if (e2 && !err) err = e2;
+    rt->flq.pop_front();
+  }
+  return err;
+}
+
+// Records the end of a flushed graph on the runtime's stream and queues it.
+// A graph on fixed buffers (a call that allocates nothing, and so creates no
+// event either) gets no end event: that call collects it before returning,
+// by waiting for the stream.
+static int enqueue_graph(dc_runtime *rt, Inflight &&f) {
+  if (f.arena >= 0) {
+    f.done = take_event(rt, false);
+    if (!f.done) return -EIO;
+    const hipError_t e = hipEventRecord(f.done, rt->stream);
+    if (e != hipSuccess) {
+      rt->ev_pool.push_back(f.done);
+      f.done = nullptr;
+      return fail_hip(e, "hipEventRecord(graph end)");
+    }
+  }
+  for (dc_handle h : f.handles) rt->handles[h - 1].inflight_ref += 1;
+  rt->flq.push_back(std::move(f));
+  return 0;
 }
 
 // Algorithmic work of a task: the operation's flop count and the bytes of
@@ -895,15 +997,6 @@ static int ensure_stream(hipStream_t *s) {
   return 0;
 }
 
-static int ensure_events(dc_runtime *rt, size_t n) {
-  while (rt->events.size() < n) {
-    hipEvent_t ev;
-    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) return -EIO;
-    rt->events.push_back(ev);
-  }
-  return 0;
-}
-
 // Lays the pending graph out for the ready-queue executor (queue.h) and
 // launches one persistent kernel per worker class present in it, all on
 // concurrent streams: the panel kernel and the GEMM kernels of each input
@@ -971,18 +1064,22 @@ static int flush_queue(dc_runtime *rt, std::chrono::steady_clock::time_point t_b
   const int64_t tail_end = off;
   const int64_t o_trace = trace ? take(nt * 3 * 8) : 0;
   const int64_t total = off;
-  if (total > rt->arena_cap) {
-    free_device(rt);
-    int64_t cap = align_up(total + total / 4, 1 << 20);
-    if (hipMalloc(&rt->arena_dev, cap) != hipSuccess) { rt->arena_dev = nullptr; return -ENOMEM; }
-    if (hipHostMalloc(&rt->arena_host, cap, hipHostMallocDefault) != hipSuccess) {
-      hipFree(rt->arena_dev);
-      rt->arena_dev = nullptr;
-      rt->arena_host = nullptr;
-      return -ENOMEM;
-    }
-    rt->arena_cap = cap;
+  int arena = -1;
+  {
+    const int er = acquire_arena(rt, total, &arena);
+    if (er) return er;
   }
+  Inflight f;
+  f.arena = arena;
+  auto fail = [&](int code) {
+    rt->arenas[arena].busy = false;
+    for (hipEvent_t ev : f.evs) rt->ev_pool.push_back(ev);
+    for (const Inflight::Timed &t : f.timed) {
+      rt->tev_pool.push_back(t.b);
+      rt->tev_pool.push_back(t.e);
+    }
+    return code;
+  };
   // CU shares.  Panel alone: its lightest instance that runs all its units,
   // as many workgroups as fit.  Otherwise every class present gets at least
   // one CU; the panel kernel gets its work's share of the CUs but at least
@@ -1026,7 +1123,7 @@ static int flush_queue(dc_runtime *rt, std::chrono::steady_clock::time_point t_b
     for (int c = 1; c < dcq::NCLASS; ++c)
       workers[c] = (int)std::min<int64_t>(citems[c], workers[c]);
   }
-  char *hb = (char *)rt->arena_host;
+  char *hb = (char *)rt->arenas[arena].host;
   TaskDesc *desc = (TaskDesc *)(hb + o_desc);
   for (int64_t t = 0; t < nt; ++t) desc[t] = rt->tasks[t].desc;
   const int64_t ticks = (int64_t)std::min<double>(
@@ -1050,10 +1147,10 @@ static int flush_queue(dc_runtime *rt, std::chrono::steady_clock::time_point t_b
   rt->last_build_ms =
       std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_build0).count();
 
-  hipError_t e = hipMemcpyAsync(rt->arena_dev, rt->arena_host, total, hipMemcpyHostToDevice,
+  hipError_t e = hipMemcpyAsync(rt->arenas[arena].dev, hb, total, hipMemcpyHostToDevice,
                                 rt->stream);
-  if (e != hipSuccess) return fail_hip(e, "hipMemcpyAsync(graph)");
-  char *db = (char *)rt->arena_dev;
+  if (e != hipSuccess) return fail(fail_hip(e, "hipMemcpyAsync(graph)"));
+  char *db = (char *)rt->arenas[arena].dev;
   QueueArgs a;
   a.desc = (const TaskDesc *)(db + o_desc);
   a.q.ctl = (dcq::Ctl *)(db + o_ctl);
@@ -1078,7 +1175,7 @@ static int flush_queue(dc_runtime *rt, std::chrono::steady_clock::time_point t_b
     if (rt->side2 == nullptr || rt->side3 == nullptr) {
       int er = ensure_stream(&rt->side2);
       if (!er) er = ensure_stream(&rt->side3);
-      if (er) return er;
+      if (er) return fail(er);
     }
     extra[0] = rt->side2;
     extra[1] = rt->side3;
@@ -1089,38 +1186,40 @@ static int flush_queue(dc_runtime *rt, std::chrono::steady_clock::time_point t_b
     }
   }
   const size_t nfork = present.size() > 1 ? present.size() : 0;
-  if (nfork && ensure_events(rt, 1 + nfork)) return -EIO;
-  if (nfork) {
-    hipEventRecord(rt->events[0], rt->stream);
-    for (int c : present)
-      if (cstream[c] != rt->stream) hipStreamWaitEvent(cstream[c], rt->events[0], 0);
+  for (size_t i = 0; i < (nfork ? 1 + nfork : 0); ++i) {
+    hipEvent_t ev = take_event(rt, false);
+    if (!ev) return fail(-EIO);
+    f.evs.push_back(ev);
   }
-  size_t ntev = 0;
-  std::vector<Inflight::Timed> timed;
-  auto tev = [&](hipStream_t st) -> size_t {
-    while (rt->tevents.size() <= ntev) {
-      hipEvent_t ev;
-      if (hipEventCreate(&ev) != hipSuccess) return SIZE_MAX;
-      rt->tevents.push_back(ev);
+  if (nfork) {
+    hipEventRecord(f.evs[0], rt->stream);
+    for (int c : present)
+      if (cstream[c] != rt->stream) hipStreamWaitEvent(cstream[c], f.evs[0], 0);
+  }
+  auto tev = [&](hipStream_t st) -> hipEvent_t {
+    hipEvent_t ev = take_event(rt, true);
+    if (!ev) return nullptr;
+    if (hipEventRecord(ev, st) != hipSuccess) {
+      rt->tev_pool.push_back(ev);
+      return nullptr;
     }
-    if (hipEventRecord(rt->tevents[ntev], st) != hipSuccess) return SIZE_MAX;
-    return ntev++;
+    return ev;
   };
   int max_workers = 0;
   // the panel kernel first: its workgroups then hold their CUs before the
   // GEMM workers spread over the rest
   for (int c : present) {
     a.cls = c;
-    const size_t tb = timing ? tev(cstream[c]) : 0;
+    hipEvent_t tb = timing ? tev(cstream[c]) : nullptr;
     const int le = c == dcq::CL_PANEL
                        ? dcx_launch_queue_panel(a, workers[c], plds, inst, cstream[c])
                        : dcx_launch_queue_gemm(a, workers[c], cstream[c]);
-    if (le != 0) return fail_hip((hipError_t)le, "queue executor launch");
+    if (le != 0) return fail(fail_hip((hipError_t)le, "queue executor launch"));
     if (timing) {
-      const size_t te = tev(cstream[c]);
-      if (tb == SIZE_MAX || te == SIZE_MAX) return -EIO;
+      hipEvent_t te = tev(cstream[c]);
+      if (!tb || !te) return fail(-EIO);
       const int k = c != dcq::CL_PANEL;
-      timed.push_back({tb, te, k, wflops[k], wbytes[k]});
+      f.timed.push_back({tb, te, k, wflops[k], wbytes[k]});
       wflops[k] = wbytes[k] = 0.0;   // a second GEMM class's launch adds nothing twice
     }
     max_workers += workers[c];
@@ -1129,13 +1228,12 @@ static int flush_queue(dc_runtime *rt, std::chrono::steady_clock::time_point t_b
     size_t j = 1;
     for (int c : present)
       if (cstream[c] != rt->stream) {
-        hipEventRecord(rt->events[j], cstream[c]);
-        hipStreamWaitEvent(rt->stream, rt->events[j], 0);
+        hipEventRecord(f.evs[j], cstream[c]);
+        hipStreamWaitEvent(rt->stream, f.evs[j], 0);
         ++j;
       }
   }
-  Inflight &f = rt->fl;
-  f.arena_dev = rt->arena_dev;
+  f.arena_dev = rt->arenas[arena].dev;
   f.tail_off = o_tail;
   f.tail_bytes = tail_end - o_tail;
   f.status_off = o_status;
@@ -1147,9 +1245,10 @@ static int flush_queue(dc_runtime *rt, std::chrono::steady_clock::time_point t_b
   f.kinds.resize(nt);
   for (int64_t t = 0; t < nt; ++t) f.kinds[t] = rt->tasks[t].desc.kind;
   f.handles = rt->touched;
-  for (dc_handle h : f.handles) rt->handles[h - 1].inflight_ref = true;
-  f.timed = std::move(timed);
-  rt->inflight = true;
+  {
+    const int er = enqueue_graph(rt, std::move(f));
+    if (er) return fail(er);
+  }
   rt->last_units = total_units;
   rt->last_workers = max_workers;
   rt->last_levels = 1;
@@ -1166,7 +1265,9 @@ extern "C" int dc_flush(dc_runtime *rt) {
     rt->slot_factor.clear();
   };
   if (rt->cfg.device < 0) { drop(); return -ENODEV; }
-  int err = finalize(rt);
+  // collect finished graphs, and wait until fewer than MAX_INFLIGHT are in
+  // flight (each holds an arena)
+  int err = collect(rt, MAX_INFLIGHT - 1);
   if (err) { drop(); return err; }
   auto t_build0 = std::chrono::steady_clock::now();
   if (rt->cfg.executor == DC_EXEC_QUEUE && !rt->ext) {
@@ -1231,27 +1332,35 @@ extern "C" int dc_flush(dc_runtime *rt) {
   // the graph's device layout goes to the runtime's arena, or to the
   // caller's fixed buffers when the call may not allocate
   const ExtArena *ext = rt->ext;
+  int arena = -1;
   if (ext) {
+    // the fixed buffers hold one graph: the one before must be collected
+    err = collect(rt, 0);
+    if (err) { drop(); return err; }
     if (total > ext->cap) {
       g_last_error = "graph layout exceeds the fixed scratch buffer";
       drop();
       return -ENOMEM;
     }
-  } else if (total > rt->arena_cap) {
-    free_device(rt);
-    int64_t cap = align_up(total + total / 4, 1 << 20);
-    if (hipMalloc(&rt->arena_dev, cap) != hipSuccess) { rt->arena_dev = nullptr; drop(); return -ENOMEM; }
-    if (hipHostMalloc(&rt->arena_host, cap, hipHostMallocDefault) != hipSuccess) {
-      hipFree(rt->arena_dev);
-      rt->arena_dev = nullptr;
-      rt->arena_host = nullptr;
-      drop();
-      return -ENOMEM;
-    }
-    rt->arena_cap = cap;
+  } else {
+    err = acquire_arena(rt, total, &arena);
+    if (err) { drop(); return err; }
   }
-  void *const arena_dev = ext ? ext->dev : rt->arena_dev;
-  char *hb = ext ? (char *)ext->host : (char *)rt->arena_host;
+  Inflight f;
+  f.arena = arena;
+  // on any failure below the arena goes back to the pool
+  auto fail = [&](int code) {
+    if (arena >= 0) rt->arenas[arena].busy = false;
+    for (hipEvent_t ev : f.evs) rt->ev_pool.push_back(ev);
+    for (const Inflight::Timed &t : f.timed) {
+      rt->tev_pool.push_back(t.b);
+      rt->tev_pool.push_back(t.e);
+    }
+    drop();
+    return code;
+  };
+  void *const arena_dev = ext ? ext->dev : rt->arenas[arena].dev;
+  char *hb = ext ? (char *)ext->host : (char *)rt->arenas[arena].host;
   TaskDesc *desc = (TaskDesc *)(hb + o_desc);
   uint64_t *items = (uint64_t *)(hb + o_items);
   std::vector<int64_t> lbegin(nl, 0);
@@ -1311,20 +1420,18 @@ extern "C" int dc_flush(dc_runtime *rt) {
   rt->last_build_ms = std::chrono::duration<double, std::milli>(t_build1 - t_build0).count();
 
   hipError_t e = hipMemcpyAsync(arena_dev, hb, total, hipMemcpyHostToDevice, rt->stream);
-  if (e != hipSuccess) { drop(); return fail_hip(e, "hipMemcpyAsync(graph)"); }
+  if (e != hipSuccess) return fail(fail_hip(e, "hipMemcpyAsync(graph)"));
   char *db = (char *)arena_dev;
   int max_workers = 0;
-  size_t nevents = 0, ntev = 0;
-  std::vector<Inflight::Timed> timed;
-  // a timing event pair around one launch on stream st
-  auto tev = [&](hipStream_t st) -> size_t {
-    while (rt->tevents.size() <= ntev) {
-      hipEvent_t ev;
-      if (hipEventCreate(&ev) != hipSuccess) return SIZE_MAX;
-      rt->tevents.push_back(ev);
+  // a timing event recorded on stream st (nullptr on failure)
+  auto tev = [&](hipStream_t st) -> hipEvent_t {
+    hipEvent_t ev = take_event(rt, true);
+    if (!ev) return nullptr;
+    if (hipEventRecord(ev, st) != hipSuccess) {
+      rt->tev_pool.push_back(ev);
+      return nullptr;
     }
-    if (hipEventRecord(rt->tevents[ntev], st) != hipSuccess) return SIZE_MAX;
-    return ntev++;
+    return ev;
   };
   auto linst = [&](int64_t L) { return lrhs[L] ? LI_RHS : llight[L] ? LI_LIGHT : LI_FULL; };
   for (int64_t L = 0; L < nl; ++L) {
@@ -1366,32 +1473,33 @@ extern "C" int dc_flush(dc_runtime *rt) {
     hipStream_t pstream = rt->stream;
     // with fixed buffers both kernels of a level run on the runtime's
     // stream, one after the other (no events to create)
+    hipEvent_t join = nullptr;
     if (hasp && hasg && !ext) {
       // fork: the panel units run on the side stream next to the GEMM units
-      while (rt->events.size() < nevents + 2) {
-        hipEvent_t ev;
-        if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) { drop(); return -EIO; }
-        rt->events.push_back(ev);
-      }
-      hipEventRecord(rt->events[nevents], rt->stream);
-      hipStreamWaitEvent(rt->side, rt->events[nevents], 0);
+      hipEvent_t fork = take_event(rt, false);
+      if (fork) f.evs.push_back(fork);
+      join = take_event(rt, false);
+      if (join) f.evs.push_back(join);
+      if (!fork || !join) return fail(-EIO);
+      hipEventRecord(fork, rt->stream);
+      hipStreamWaitEvent(rt->side, fork, 0);
       pstream = rt->side;
     }
     if (hasp) {
       a.begin = lbegin[L];
       a.count = pcount[L];
       a.counter = (unsigned long long *)(db + o_cnt) + 4 * L;
-      const size_t tb = timing ? tev(pstream) : 0;
+      hipEvent_t tb = timing ? tev(pstream) : nullptr;
       int le = dcx_launch_level(a, pworkers, llds[L], linst(L), pstream);
-      if (le != 0) { fail_hip((hipError_t)le, "level launch"); drop(); return -EIO; }
+      if (le != 0) return fail(fail_hip((hipError_t)le, "level launch"));
       if (timing) {
-        const size_t te = tev(pstream);
-        if (tb == SIZE_MAX || te == SIZE_MAX) { drop(); return -EIO; }
-        timed.push_back({tb, te, 0, wflops[2 * L], wbytes[2 * L]});
+        hipEvent_t te = tev(pstream);
+        if (!tb || !te) return fail(-EIO);
+        f.timed.push_back({tb, te, 0, wflops[2 * L], wbytes[2 * L]});
       }
     }
     if (hasg) {
-      const size_t tb = timing ? tev(rt->stream) : 0;
+      hipEvent_t tb = timing ? tev(rt->stream) : nullptr;
       const int64_t n64 = g64count[L], n32 = g32count[L], nlp = gcount[L] - n64 - n32;
       int64_t begin = gbegin[L];
       for (int v = 0; v < 3; ++v) {
@@ -1404,25 +1512,22 @@ extern "C" int dc_flush(dc_runtime *rt) {
           gworkers = std::max(gworkers, wg);
           const int le = v < 2 ? dcx_launch_gemm(a, wg, v == 0 ? T_F64 : T_F32, rt->stream)
                                : dcx_launch_gemm_lowp(a, wg, rt->stream);
-          if (le != 0) { fail_hip((hipError_t)le, "gemm launch"); drop(); return -EIO; }
+          if (le != 0) return fail(fail_hip((hipError_t)le, "gemm launch"));
         }
         begin += cnt;
       }
       if (timing) {
-        const size_t te = tev(rt->stream);
-        if (tb == SIZE_MAX || te == SIZE_MAX) { drop(); return -EIO; }
-        timed.push_back({tb, te, 1, wflops[2 * L + 1], wbytes[2 * L + 1]});
+        hipEvent_t te = tev(rt->stream);
+        if (!tb || !te) return fail(-EIO);
+        f.timed.push_back({tb, te, 1, wflops[2 * L + 1], wbytes[2 * L + 1]});
       }
     }
-    if (hasp && hasg && !ext) {
-      // join
-      hipEventRecord(rt->events[nevents + 1], rt->side);
-      hipStreamWaitEvent(rt->stream, rt->events[nevents + 1], 0);
-      nevents += 2;
+    if (join) {
+      hipEventRecord(join, rt->side);
+      hipStreamWaitEvent(rt->stream, join, 0);
     }
     max_workers = std::max(max_workers, pworkers + gworkers);
   }
-  Inflight &f = rt->fl;
   f.arena_dev = arena_dev;
   f.tail_off = o_tail;
   f.tail_bytes = tail_end - o_tail;
@@ -1435,9 +1540,8 @@ extern "C" int dc_flush(dc_runtime *rt) {
   f.kinds.resize(nt);
   for (int64_t t = 0; t < nt; ++t) f.kinds[t] = rt->tasks[t].desc.kind;
   f.handles = rt->touched;
-  for (dc_handle h : f.handles) rt->handles[h - 1].inflight_ref = true;
-  f.timed = std::move(timed);
-  rt->inflight = true;
+  err = enqueue_graph(rt, std::move(f));
+  if (err) return fail(err);
   rt->last_units = total_units;
   rt->last_workers = max_workers;
   rt->last_levels = nl;
@@ -1449,7 +1553,7 @@ extern "C" int dc_wait_all(dc_runtime *rt) {
   if (!rt) return -EINVAL;
   int e = dc_flush(rt);
   if (e) return e;
-  return finalize(rt);
+  return collect(rt, 0);
 }
 
 extern "C" const char *dc_strerror(int err) {

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <deque>
 #include <string>
 #include <unordered_map>
 #include <vector>
@@ -42,8 +43,8 @@ struct Handle {
   int64_t last_writer = -1;
   std::vector<int64_t> readers;
   int pending = 0;
-  // referenced by the graph that was flushed and may still be running
-  bool inflight_ref = false;
+  // flushed graphs not yet collected that reference this handle
+  int inflight_ref = 0;
   // numerical status of the last factorisation (top-level handles)
   int64_t info = 0;
   // top-level handle whose numerical status this handle's tasks share (0:
@@ -66,16 +67,31 @@ struct ExtArena {
   int64_t cap = 0;
 };
 
+// Device and pinned host memory holding one graph's layout.
+struct Arena {
+  void *dev = nullptr;
+  void *host = nullptr;
+  int64_t cap = 0;
+  bool busy = false;               // a graph in flight uses it
+};
+
+// Graphs flushed and not yet collected, at most this many per runtime.
+constexpr size_t MAX_INFLIGHT = 8;
+
+// One flushed graph until it is collected.
 struct Inflight {
   void *arena_dev = nullptr;       // where the graph's layout lives
+  int arena = -1;                  // index in dc_runtime::arenas, -1 for fixed buffers
   int64_t tail_off = 0, tail_bytes = 0, status_off = 0, info_off = 0, trace_off = 0;
   int64_t ntasks = 0;
   std::vector<dc_handle> slot_roots;
   std::vector<char> slot_factor;   // slot has a POTRF task in the graph
   std::vector<int32_t> kinds;
   std::vector<dc_handle> handles;  // handles the flushed graph references
+  hipEvent_t done = nullptr;       // recorded after the graph's last launch
+  std::vector<hipEvent_t> evs;     // its fork/join events
   // timed launches: (begin event, end event, kernel class, flops, bytes)
-  struct Timed { size_t b, e; int cls; double flops, bytes; };
+  struct Timed { hipEvent_t b, e; int cls; double flops, bytes; };
   std::vector<Timed> timed;
 };
 
@@ -84,9 +100,9 @@ struct dc_runtime {
   hipStream_t stream = nullptr;
   hipStream_t side = nullptr;                  // panel units next to GEMM units
   hipStream_t side2 = nullptr, side3 = nullptr; // further concurrent worker classes
-  std::vector<hipEvent_t> events;              // fork/join events, reused per flush
+  std::vector<hipEvent_t> ev_pool;             // free events without timing
   bool ktiming = false;                        // per-kernel timing enabled
-  std::vector<hipEvent_t> tevents;             // timing events, reused per flush
+  std::vector<hipEvent_t> tev_pool;            // free timing events
   dc_kernel_stats kstats{};
   bool own_stream = false;
   int num_cus = 0;
@@ -102,15 +118,12 @@ struct dc_runtime {
   std::vector<dc_handle> slot_roots;
   std::vector<char> slot_factor;
 
-  void *arena_dev = nullptr;
   void *inv_ws = nullptr;                      // dc_potrf's inverse workspace
   int64_t inv_ws_bytes = 0;
   void *mix_ws = nullptr;                      // dc_potrf's mixed-precision workspace
   int64_t mix_ws_bytes = 0;
-  void *arena_host = nullptr;
-  int64_t arena_cap = 0;
-  bool inflight = false;
-  Inflight fl;
+  std::vector<Arena> arenas;                   // at most MAX_INFLIGHT
+  std::deque<Inflight> flq;                    // flushed graphs, oldest first
   const ExtArena *ext = nullptr;               // set for the duration of a no-alloc call
 
   std::vector<int64_t> trace_host;

@@ -488,7 +488,7 @@ extern "C" int dc_server_create(dc_server **out, const dc_server_config *cfg) {
   dc_server_config c;
   if (cfg) c = *cfg; else dc_server_config_default(&c);
   if (c.slots < 1 || c.slots > 64 || c.tile < 1 || c.tile > dcx::MAX_TILE || c.pool_bytes == 0 ||
-      c.whole_max < 0 || c.whole_max > dcx::MAX_TILE ||
+      c.whole_max < 0 || c.whole_max > dcx::MAX_TILE || c.mixed_min < 0 ||
       !(c.tol > 0) || c.maxit < 0 || (c.upd != DC_F64 && c.upd != DC_F32 && c.upd != DC_BF16))
     return -EINVAL;
   dc_server *srv = new (std::nothrow) dc_server();
@@ -532,7 +532,9 @@ extern "C" double dc_server_now(dc_server *srv) { return srv ? srv->now() : 0.0;
 extern "C" int dc_server_submit(dc_server *srv, const dc_request *req, int64_t *id) {
   if (!srv || !req || !id || req->n < 1 || req->r < 1 || !req->A || !req->B || !req->X)
     return -EINVAL;
-  const dc_dtype prec = (dc_dtype)srv->cfg.upd;
+  // low-precision updates only where the factorisation is large enough for
+  // them to pay for the extra refinement steps
+  const dc_dtype prec = req->n < srv->cfg.mixed_min ? DC_F64 : (dc_dtype)srv->cfg.upd;
   if (footprint(srv->cfg, req->n, req->r, DC_F64) > srv->cfg.pool_bytes) return -ENOMEM;
   Request q;
   q.id = srv->next_id++;

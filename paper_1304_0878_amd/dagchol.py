@@ -66,7 +66,8 @@ class dc_kernel_stats(ctypes.Structure):
 class dc_server_config(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int), ("slots", ctypes.c_int), ("pool_bytes", ctypes.c_size_t),
                 ("tile", ctypes.c_int64), ("upd", ctypes.c_int), ("tol", ctypes.c_double),
-                ("maxit", ctypes.c_int), ("whole_max", ctypes.c_int64)]
+                ("maxit", ctypes.c_int), ("whole_max", ctypes.c_int64),
+                ("mixed_min", ctypes.c_int64)]
 
 
 class dc_request(ctypes.Structure):
@@ -407,8 +408,9 @@ def posv_ir(rt, a, b, x, tile, upd=DC_F32, tol=1e-12, maxit=30):
 
 
 def potrf_batched(rt, mats, rhs=None, tiles=None):
-    """Factors every CUDA float64 matrix of ``mats`` in place (and solves the
-    matching ``rhs`` in place) in one graph; returns the per-matrix infos."""
+    """Factors every CUDA float64 or float32 matrix of ``mats`` in place (and
+    solves the matching float64 ``rhs`` in place) in one graph; returns the
+    per-matrix infos.  Float32 matrices are factored as one tile."""
     ha = [rt.register_tensor(m) for m in mats]
     hb = [rt.register_tensor(b) for b in rhs] if rhs is not None else None
     try:
@@ -425,13 +427,15 @@ class Server:
     submit() are kept alive here until their request completes."""
 
     def __init__(self, device=0, slots=4, pool_bytes=None, tile=256, upd=DC_F32, tol=1e-12,
-                 maxit=30, whole_max=None):
+                 maxit=30, whole_max=None, mixed_min=None):
         cfg = dc_server_config()
         _lib.dc_server_config_default(ctypes.byref(cfg))
         cfg.device, cfg.slots, cfg.tile, cfg.upd = device, slots, tile, upd
         cfg.tol, cfg.maxit = tol, maxit
         if whole_max is not None:
             cfg.whole_max = whole_max
+        if mixed_min is not None:
+            cfg.mixed_min = mixed_min
         if pool_bytes is not None:
             cfg.pool_bytes = pool_bytes
         p = _P()

@@ -150,10 +150,10 @@ def test_error_codes(dc):
         rt.dc_unregister(a)
         with pytest.raises(dc.DagcholError):
             rt.dc_task_submit(dc.DC_POTRF, [a], [dc.DC_RW])
-        b = rt.dc_matrix_register(FAKE * 5, 10, 10, 10, dc.DC_F32)
+        b = rt.dc_matrix_register(FAKE * 5, 10, 10, 10, dc.DC_BF16)
         with pytest.raises(dc.DagcholError) as e:
             rt.dc_task_submit(dc.DC_POTRF, [b], [dc.DC_RW])
-        assert e.value.code == -22  # POTRF needs FP64
+        assert e.value.code == -22  # POTRF needs FP64 or FP32 storage
 
 
 def test_ragged_partition_shapes(dc):

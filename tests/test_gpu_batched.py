@@ -127,3 +127,59 @@ def test_batched_at_tuner_tiles_matches_oracle(dc, rt, torch_dev):
         lr = np.tril(core.potrf_tiled(a, t or n)[0])
         xr = core.potrs_tiled(lr, b, t or n)
         assert np.abs(x - xr).max() / np.abs(xr).max() <= 16 * n * U * np.linalg.cond(a)
+
+
+def test_batched_fp32_and_fp64_in_one_graph(dc, rt, torch_dev):
+    """FP32 matrices (factored as one tile: FP64 arithmetic, the factor
+    rounded to FP32) next to FP64 ones in one call.  FP32 bars: backward
+    error of the stored factor ||A32 - L L^T||_F / ||A32||_F <= 4 n u32
+    (u32 = 2^-24: one rounding per stored entry, amplified by the
+    recurrence) and the solution (FP64 arithmetic on the FP32 factor) within
+    8 n u32 cond(A) of the oracle's FP64 solution of the same matrix; the
+    FP64 matrices as in the FP64-only batches, and bit-identical to their
+    factor in an FP64-only batch."""
+    torch, dev = torch_dev
+    ns, mats, rhs = _batch(48, 6, nmax=512)
+    is32 = [i % 2 == 0 for i in range(len(ns))]
+    ta = [torch.from_numpy(m).to(dev).to(torch.float32) if f else torch.from_numpy(m).to(dev)
+          for m, f in zip(mats, is32)]
+    tb = [torch.from_numpy(b).to(dev) for b in rhs]
+    infos = dc.potrf_batched(rt, ta, tb, [0] * len(ns))
+    assert infos == [0] * len(ns)
+    U32 = 2.0 ** -24
+    for i, (n, a, b) in enumerate(zip(ns, mats, rhs)):
+        l = np.tril(ta[i].cpu().numpy().astype(np.float64))
+        x = tb[i].cpu().numpy()
+        if is32[i]:
+            a32 = a.astype(np.float32).astype(np.float64)
+            assert core.backward_error_fro(a32, l) <= 4 * n * U32
+            assert np.array_equal(l, l.astype(np.float32).astype(np.float64))
+            lr = np.tril(core.potrf_tiled(a32, n)[0])
+            xr = core.potrs_tiled(lr, b, n)
+            cond = np.linalg.cond(a32)
+            assert np.abs(x - xr).max() / np.abs(xr).max() <= 8 * n * U32 * cond
+        else:
+            assert core.backward_error_fro(a, l) <= 1e-13
+    # the FP64 matrices are unchanged by their FP32 neighbours
+    idx = [i for i in range(len(ns)) if not is32[i]]
+    _, l64, x64 = _run(dc, rt, torch_dev, [mats[i] for i in idx], [rhs[i] for i in idx],
+                       [0] * len(idx))
+    for k, i in enumerate(idx):
+        assert np.array_equal(np.tril(ta[i].cpu().numpy()), l64[k])
+
+
+def test_batched_fp32_integer_exact(dc, rt, torch_dev):
+    """Integer factors with entries and partial sums exact in FP32: the FP32
+    factor is L0 bit for bit and the solution the integer one."""
+    torch, dev = torch_dev
+    mats, rhs, sols = [], [], []
+    for i, n in enumerate((24, 100, 300)):
+        a, l0 = inputs.integer_factor(n, 70 + i, diag_choices=(1.0, 2.0))
+        x0 = inputs.integer_solution(n, 2, 80 + i)
+        mats.append(torch.from_numpy(a).to(dev).to(torch.float32))
+        rhs.append(torch.from_numpy(a @ x0).to(dev))
+        sols.append((l0, x0))
+    assert dc.potrf_batched(rt, mats, rhs, [0, 0, 0]) == [0, 0, 0]
+    for (l0, x0), m, b in zip(sols, mats, rhs):
+        assert np.array_equal(np.tril(m.cpu().numpy().astype(np.float64)), l0)
+        assert np.array_equal(b.cpu().numpy(), x0)
