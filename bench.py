@@ -25,6 +25,15 @@ import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
+# The serving leg runs eight slot runtimes, each on its own streams: give the
+# process enough hardware queues for them to run side by side (HIP reads
+# this when it starts; the default is 4).
+os.environ.setdefault("GPU_MAX_HW_QUEUES", "16")
+
+
+def progress(msg):
+    """One line per finished measurement, on stderr."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
 FP64_PEAK_TFLOPS = 78.6   # MI355X dense FP64 matrix peak (published)
 FP32_PEAK_TFLOPS = 157.3  # MI355X dense FP32 matrix peak (published)
@@ -407,13 +416,14 @@ def leg_batched(torch, dagchol, dev, seed, count, reps):
 
 
 def leg_serving(torch, dagchol, dev, seed, nreq, nmax, npool=96, sweep=(0.5, 0.9, 1.2),
-                mixed_min=0):
+                mixed_min=0, sweep_requests=1000):
     """Open-loop serving: requests (n log-uniform in [32, nmax], 1-8
     right-hand sides, cond 10^U(2, 6)) drawn from a device-resident pool of
     `npool` matrices generated before the timed runs.  The saturated
-    throughput mu64 of the FP64 path is measured first (all requests at
+    throughput mu64 of the FP64 path is measured first (`nreq` requests at
     t = 0), then the mixed path's; both paths then serve the same Poisson
-    arrival stream at lambda = f * mu64 for each f of `sweep`.  Latency =
+    arrival stream of `sweep_requests` requests at lambda = f * mu64 for
+    each f of `sweep`.  Latency =
     completion - arrival; p50/p99 by nearest rank over all requests."""
     import math as _m
     import numpy as np
@@ -433,9 +443,10 @@ def leg_serving(torch, dagchol, dev, seed, nreq, nmax, npool=96, sweep=(0.5, 0.9
         b_i = torch.randn(a_i.shape[0], r_i, dtype=torch.float64, device=dev, generator=g)
         reqs.append((a_i, b_i, torch.zeros_like(b_i)))
     torch.cuda.synchronize()
-    flop = sum(flops_potrf(a.shape[0]) + 4.0 * a.shape[0] ** 2 * b.shape[1] for a, b, _ in reqs)
+    flop = [flops_potrf(a.shape[0]) + 4.0 * a.shape[0] ** 2 * b.shape[1] for a, b, _ in reqs]
 
     def serve(upd, arrivals):
+        nreq = len(arrivals)
         srv = dagchol.Server(device=0, slots=8, pool_bytes=96 << 30, tile=256, upd=upd,
                              tol=1e-12, maxit=30, mixed_min=mixed_min)
         t0 = srv.now()
@@ -454,23 +465,25 @@ def leg_serving(torch, dagchol, dev, seed, nreq, nmax, npool=96, sweep=(0.5, 0.9
         bad = [d for d in done if d["status"] != 0 or not d["converged"]]
         rank = lambda q: lat[max(0, min(len(lat) - 1, int(math.ceil(q * len(lat))) - 1))]
         worst = 0.0
-        for a_i, b_i, x_i in reqs[:: max(1, nreq // 32)]:
+        for a_i, b_i, x_i in reqs[:nreq:max(1, nreq // 32)]:
             r = b_i - a_i @ x_i
             worst = max(worst, float(r.abs().max() / (a_i.abs().sum(1).max() * x_i.abs().max()
                                                       + b_i.abs().max())))
-        return {"solves_per_s": round(nreq / span, 2),
+        progress(f"serving {'fp64' if upd == dagchol.DC_F64 else 'mixed'}: "
+                 f"{len(done)} requests in {span:.1f} s")
+        return {"requests": len(done), "solves_per_s": round(len(done) / span, 2),
                 "p50_ms": round(rank(0.50) * 1e3, 2),
                 "p99_ms": round(rank(0.99) * 1e3, 2),
                 "unconverged_or_failed": len(bad),
                 "restarts": sum(d["restarts"] for d in done),
-                "gflops": round(flop / span / 1e9, 1),
+                "gflops": round(sum(flop[:nreq]) / span / 1e9, 1),
                 "worst_backward_error_sample": worst}
 
     zero = [0.0] * nreq
     sat64 = serve(dagchol.DC_F64, zero)
     sat32 = serve(dagchol.DC_F32, zero)
     mu = sat64["solves_per_s"]
-    gaps = rng.exponential(1.0, nreq)
+    gaps = rng.exponential(1.0, sweep_requests)
     unit = list(np.cumsum(gaps) - gaps[0])      # arrivals of a rate-1 Poisson stream
     opened = {}
     for f in sweep:
@@ -559,20 +572,25 @@ def main():
         eta = float(torch.linalg.matrix_norm(r) / torch.linalg.matrix_norm(az))
         del low
     torch.cuda.synchronize()
+    progress(f"FP64 factorisation: {ms:.1f} ms per step")
     legs = [v for v in args.legs.split(",") if v and v != "none"]
     extra = {}
     if "mixed" in legs:
         extra["mixed_precision"] = leg_mixed(torch, dagchol, rt, stream, a0, a, n, tile,
                                              args.seed, lam, delta)
+        progress("mixed precision done")
     rt.close()
     del a
     torch.cuda.empty_cache()
     if "small" in legs:
         extra["n512_latency"] = leg_small(torch, dagchol, dev, args.seed)
+        progress("n=512 latency done")
     if "n8192" in legs:
         extra["n8192"] = leg_8192(torch, dagchol, dev, args.seed)
+        progress("n=8192 done")
     if "batched" in legs:
         extra["batched"] = leg_batched(torch, dagchol, dev, args.seed, args.batch_count, 3)
+        progress("batched done")
     if "serving" in legs:
         del a0
         torch.cuda.empty_cache()
@@ -620,6 +638,7 @@ def main():
     out.update(extra)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
+        progress("CPU baseline done")
     print(json.dumps(out), flush=True)
 
 

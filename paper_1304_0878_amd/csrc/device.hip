@@ -88,6 +88,14 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Value of v on lane `lane` (a constant), in every lane.
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffff), lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 // ------------------------------------------------------------------ TRSM
 //
 // X (m x nb) <- X L^{-T}; unit = 16 consecutive rows of X held in LDS.
@@ -484,6 +492,265 @@ __device__ __forceinline__ void run_trsm_inv(const TaskDesc &d, int unit, double
 
 // ----------------------------------------------------------------- POTRF
 //
+// Register-resident POTRF of a diagonal tile of order nb <= RPOTRF_MAX.  The
+// lower triangle is cut into 16x16 blocks (I, J), J <= I, of MB block rows.
+// Block column 0 goes from memory straight to LDS; the blocks with J >= 1,
+// numbered column by column from (1, 1), live in MFMA accumulators: block b
+// in slot b / 4 of wave b % 4 (lane l holds rows 16I + l/16 + 4e, e = 0..3,
+// of column 16J + l%16: the result layout of v_mfma_f64_16x16x4f64).
+// Right-looking over the block columns k:
+//  (1) the blocks of column k are published to LDS;
+//  (2) the first wave factors the diagonal block in registers, lane i
+//      holding row i: for each column j the pivot is taken from lane j, its
+//      square root and reciprocal are formed once, column j is scaled, and
+//      the columns right of it take a rank-one update whose column-j entries
+//      come from their lanes (readlane); the block is stored, and published
+//      with the reciprocals of its diagonal for step (3);
+//  (3) every thread takes one row below the diagonal block and solves it by
+//      substitution in the same column order (multiplying by the published
+//      reciprocals), then stores and publishes it;
+//  (4) each wave subtracts P_I P_J^T from its blocks right of column k with
+//      four MFMAs (K = 16), reading the next block's operands before the
+//      current block's products.
+// Rows and columns beyond nb are padded with the identity, which factors to
+// itself and leaves the real entries unchanged.  Returns 0, or the 1-based
+// column (within the tile) of the first non-positive or NaN pivot; the block
+// columns left of that pivot's block hold their final values.
+constexpr int RP_MB = RPOTRF_MAX / 16;
+constexpr int RP_SLOTS = (RP_MB * (RP_MB - 1) / 2 + 3) / 4;   // 30
+constexpr int RP_LD = PANEL + 1;                              // 17
+constexpr int RP_GROUP = 6;                                  // slots loaded together
+
+typedef double dvec4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ dvec4 mfma16(double a, double b, dvec4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// Moves (I, J) forward by `step` blocks in the column-by-column numbering of
+// the lower triangle of MB block rows; J == MB once past the last block.
+// Every argument is wave-uniform, so this is scalar arithmetic.
+__device__ __forceinline__ void rp_advance(int &I, int &J, int step, int MB) {
+  I += step;
+  while (J < MB && I >= MB) {
+    I = I - MB + J + 1;
+    J += 1;
+  }
+}
+
+template <typename TS>
+__device__ __forceinline__ int run_potrf_regs(const TaskDesc &d, double *lds) {
+  const int nb = d.m;
+  gptr<TS> D = (gptr<TS>)d.c;
+  const int64_t ldd = d.ldc;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int l16 = lane & 15, kq = lane >> 4;
+  const int MB = __builtin_amdgcn_readfirstlane((nb + 15) / 16);
+  const int npad = 16 * MB;
+  // two panel buffers of npad rows (step k uses buffer k % 2; addresses are
+  // formed from lds so that they stay LDS addresses)
+  const int pbuf = npad * RP_LD;
+  // pivot block: row i of L_kk in Ds[i][0..i], 1 / l_ii in Ds[i][16]
+  double *Ds = lds + 2 * pbuf;
+  int *flag = (int *)(Ds + PANEL * (PANEL + 1));
+  // first slot of this wave: block w of the numbering from (1, 1)
+  int I0 = 1, J0 = 1;
+  rp_advance(I0, J0, w, MB);
+
+  // block column 0 into the first panel buffer (identity padding): thread t
+  // takes elements t, t + NT, ..., four loads (clamped in bounds) issued
+  // before their LDS writes
+  {
+    constexpr int PER = RPOTRF_MAX * PANEL / NT;   // 16
+#pragma unroll
+    for (int q0 = 0; q0 < PER; q0 += 4) {
+      double v[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int idx = tid + (q0 + q) * NT, row = idx >> 4, col = idx & 15;
+        v[q] = (double)D[(int64_t)min(row, nb - 1) * ldd + min(col, nb - 1)];
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int idx = tid + (q0 + q) * NT, row = idx >> 4, col = idx & 15;
+        if (row < npad)
+          lds[row * RP_LD + col] =
+              row < nb && col < nb && col <= row ? v[q] : (row == col ? 1.0 : 0.0);
+      }
+      if ((q0 + 4) * NT >= npad * PANEL) break;
+    }
+  }
+  // the other blocks into the accumulators, RP_GROUP slots at a time: every
+  // element read is in bounds (indices clamped), so a group's loads carry no
+  // branches and issue back to back
+  dvec4 acc[RP_SLOTS];
+  {
+    int I = I0, J = J0;
+#pragma unroll
+    for (int g = 0; g < RP_SLOTS; g += RP_GROUP) {
+      if (J < MB) {
+#pragma unroll
+        for (int s = g; s < g + RP_GROUP && s < RP_SLOTS; ++s) {
+          const bool valid = J < MB;
+          const int col = 16 * J + l16;
+          const int colc = min(col, nb - 1);
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int row = 16 * I + kq + 4 * e;
+            const double v = (double)D[(int64_t)min(row, nb - 1) * ldd + colc];
+            acc[s][e] = valid && row < nb && col < nb && col <= row ? v : (row == col ? 1.0 : 0.0);
+          }
+          rp_advance(I, J, 4, MB);
+        }
+      } else {
+#pragma unroll
+        for (int s = g; s < g + RP_GROUP && s < RP_SLOTS; ++s) acc[s] = (dvec4){0.0, 0.0, 0.0, 0.0};
+      }
+    }
+  }
+
+  int bad = 0;
+  for (int k = 0; k < MB; ++k) {
+    double *Pk = lds + (k & 1) * pbuf;
+    // (1) publish block column k (block rows k .. MB - 1) to LDS
+    if (k > 0) {
+      int I = I0, J = J0;
+#pragma unroll
+      for (int s = 0; s < RP_SLOTS; ++s) {
+        if (J == k) {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) Pk[(16 * I + kq + 4 * e) * RP_LD + l16] = acc[s][e];
+        }
+        rp_advance(I, J, 4, MB);
+      }
+    }
+    __syncthreads();
+    // (2) the first wave factors the diagonal block; lane i holds row i
+    // (lanes 16..63 repeat rows 0..15 and store nothing)
+    if (w == 0) {
+      const int i = l16;
+      double v[PANEL];
+#pragma unroll
+      for (int j = 0; j < PANEL; ++j) v[j] = Pk[(16 * k + i) * RP_LD + j];
+      double rinv = 0.0;
+      int f = 0;
+      // no early exit (it would keep the loop from unrolling): after a
+      // failed pivot the rest is computed on garbage and not stored
+#pragma unroll
+      for (int j = 0; j < PANEL; ++j) {
+        const double piv = readlane_f64(v[j], j);
+        if (!(piv > 0.0) && f == 0) f = j + 1;   // non-positive or NaN: uniform
+        const double djj = sqrt(piv);
+        const double rj = 1.0 / djj;
+        v[j] = i == j ? djj : v[j] * rj;
+        if (i == j) rinv = rj;
+        // rank-one update of the columns right of j (entries above the
+        // diagonal take garbage and are never read)
+#pragma unroll
+        for (int p = j + 1; p < PANEL; ++p) v[p] = fma(-v[j], readlane_f64(v[j], p), v[p]);
+        // keep each column's readlanes next to their uses: hoisted, they
+        // exhaust the scalar registers
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      if (!f && kq == 0) {
+        const int row = 16 * k + i;
+#pragma unroll
+        for (int j = 0; j < PANEL; ++j) {
+          const double x = j <= i ? v[j] : 0.0;
+          Ds[i * RP_LD + j] = x;
+          if (j <= i && row < nb) D[(int64_t)row * ldd + 16 * k + j] = (TS)x;
+        }
+        Ds[i * RP_LD + PANEL] = rinv;
+      }
+      if (lane == 0) *flag = f;
+    }
+    __syncthreads();
+    {
+      const int f = *flag;
+      if (f) {
+        // a pivot inside the padding cannot fail (it is 1)
+        bad = 16 * k + f;
+        break;
+      }
+    }
+    // (3) rows below the diagonal block, one per thread, by substitution
+    // with the published factor
+    {
+      const int row = 16 * (k + 1) + tid;
+      if (row < npad) {
+        double x[PANEL];
+#pragma unroll
+        for (int j = 0; j < PANEL; ++j) x[j] = Pk[row * RP_LD + j];
+#pragma unroll
+        for (int j = 0; j < PANEL; ++j) {
+          x[j] *= Ds[j * RP_LD + PANEL];
+#pragma unroll
+          for (int p = j + 1; p < PANEL; ++p) x[p] = fma(-x[j], Ds[p * RP_LD + j], x[p]);
+        }
+#pragma unroll
+        for (int j = 0; j < PANEL; ++j) Pk[row * RP_LD + j] = x[j];
+        if (row < nb) {
+          gptr<TS> Dr = D + (int64_t)row * ldd + 16 * k;
+          if (16 * k + PANEL <= nb) {
+#pragma unroll
+            for (int j = 0; j < PANEL; ++j) Dr[j] = (TS)x[j];
+          } else {
+            // the last block column is narrower than 16
+            for (int j = 0; j < nb - 16 * k; ++j) Dr[j] = (TS)Pk[row * RP_LD + j];
+          }
+        }
+      }
+    }
+    __syncthreads();
+    // (4) trailing update of this wave's blocks right of column k; the
+    // operands of the next live slot are read before the current slot's
+    // MFMAs (slots are numbered column by column, so the live ones, J > k,
+    // are the last valid ones)
+    {
+      int I = I0, J = J0;
+      auto rowa = [&](int Ib) { return (16 * Ib + l16) * RP_LD + kq; };
+      double an[4] = {0.0, 0.0, 0.0, 0.0}, bn[4] = {0.0, 0.0, 0.0, 0.0};
+      if (J < MB && J > k) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          an[q] = Pk[rowa(I) + 4 * q];
+          bn[q] = Pk[rowa(J) + 4 * q];
+        }
+      }
+#pragma unroll
+      for (int s = 0; s < RP_SLOTS; ++s) {
+        double a[4], b[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          a[q] = an[q];
+          b[q] = bn[q];
+        }
+        const bool live = J < MB && J > k;
+        int I2 = I, J2 = J;
+        rp_advance(I2, J2, 4, MB);
+        if (s + 1 < RP_SLOTS && J2 < MB && J2 > k) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            an[q] = Pk[rowa(I2) + 4 * q];
+            bn[q] = Pk[rowa(J2) + 4 * q];
+          }
+        }
+        if (live) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) acc[s] = mfma16(-a[q], b[q], acc[s]);
+        }
+        I = I2;
+        J = J2;
+      }
+    }
+  }
+  __syncthreads();
+  return bad;
+}
+
+// Left-looking POTRF (any order up to MAX_TILE).
+//
 // D (nb x nb, lower) = L L^T in place.  Left-looking over 16-column panels:
 // (1) D[c0:, c0:c0+16] -= D[c0:, :c0] D[c0:c0+16, :c0]^T with MFMA: the 16
 // pivot rows are staged in LDS, each wave takes every fourth 16-row group
@@ -693,14 +960,6 @@ __device__ __forceinline__ void solve_stage(double *Bs, const gdouble *Bm, int64
 // row at a time, x_i = t_i * (1 / l_ii) on lane i shared across its column
 // group, the other rows dropping their terms in x_i.  FORWARD: rows top down,
 // lrow[i] = l_qi; otherwise bottom up with lrow[i] = l_iq.
-// Value of v on lane `lane` (a constant), in every lane.
-__device__ __forceinline__ double readlane_f64(double v, int lane) {
-  const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffff), lane);
-  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-
 template <bool FORWARD>
 __device__ __forceinline__ void solve_block(double *Bs, const double *part, const double *Ljj,
                                             int i0, int h, int rc) {
@@ -1250,14 +1509,14 @@ template <int MODE>
 __device__ __forceinline__ void run_panel_unit(const TaskDesc &d, int u, double *lds,
                                                int64_t *info, int32_t *failed) {
   const int kind = __builtin_amdgcn_readfirstlane(d.kind);
-  if (MODE != LI_RHS) switch (kind) {
+  if (MODE == LI_FULL || MODE == LI_LIGHT) switch (kind) {
     case K_SCAL: run_scal(d, u); break;
     case K_CAST: run_cast(d, u); break;
     case K_RESID: run_resid(d, u, lds); break;
     case K_AXPY: run_axpy(d, u); break;
     default: break;
   }
-  if (MODE != LI_LIGHT) switch (kind) {
+  if (MODE == LI_FULL || MODE == LI_RHS) switch (kind) {
     case K_GEMM_RHS_N:
       if (d.ta == T_F32) run_gemm_rhs_n<float>(d, u, lds); else run_gemm_rhs_n<double>(d, u, lds);
       break;
@@ -1288,12 +1547,26 @@ __device__ __forceinline__ void run_panel_unit(const TaskDesc &d, int u, double 
     }
     default: break;
   }
+  // POTRF units of order <= RPOTRF_MAX in an instance of their own, whose
+  // registers all go to the register-resident factor (the runtime sends
+  // larger ones to the full instance; one arriving here is reported as a
+  // breakdown at its first column rather than left unfactored)
+  if (MODE == LI_POTRF && kind == K_POTRF) {
+    const int bad = __builtin_amdgcn_readfirstlane(d.m) > RPOTRF_MAX ? 1
+                    : d.tc == T_F32 ? run_potrf_regs<float>(d, lds)
+                                    : run_potrf_regs<double>(d, lds);
+    if (bad && threadIdx.x == 0 && d.matrix >= 0) {
+      info[d.matrix] = d.row0 + bad;
+      failed[d.matrix] = 1;
+    }
+  }
 }
 
 // Level executor: the workgroups of one level launch take the level's
 // units through an atomic counter until the list is exhausted.
 template <int MODE>
-__global__ void __launch_bounds__(NT, MODE == LI_FULL ? 1 : 4) dc_level_kernel(LevelArgs A) {
+__global__ void __launch_bounds__(NT, (MODE == LI_FULL || MODE == LI_POTRF) ? 1 : 4)
+    dc_level_kernel(LevelArgs A) {
   extern __shared__ double lds[];
   __shared__ uint64_t s_idx;
   __shared__ int s_skip;
@@ -1328,7 +1601,8 @@ __global__ void __launch_bounds__(NT, MODE == LI_FULL ? 1 : 4) dc_level_kernel(L
 // and thread 0 completes the item (releasing successors).  The worker
 // leaves when every panel item has been claimed or the watchdog fired.
 template <int MODE>
-__global__ void __launch_bounds__(NT, MODE == LI_FULL ? 1 : 4) dc_queue_panel_kernel(QueueArgs A) {
+__global__ void __launch_bounds__(NT, (MODE == LI_FULL || MODE == LI_POTRF) ? 1 : 4)
+    dc_queue_panel_kernel(QueueArgs A) {
   extern __shared__ double lds[];
   __shared__ uint64_t s_item;
   __shared__ int s_skip;
@@ -1380,7 +1654,10 @@ extern "C" int dc_selftest(void *dev_ptr, int64_t n, void *stream) {
 
 int dcx_launch_level(const LevelArgs &args, int workers, size_t lds_bytes, int inst,
                      void *stream) {
-  if (inst == LI_LIGHT)
+  if (inst == LI_POTRF)
+    hipLaunchKernelGGL(dc_level_kernel<LI_POTRF>, dim3(workers), dim3(NT), lds_bytes,
+                       (hipStream_t)stream, args);
+  else if (inst == LI_LIGHT)
     hipLaunchKernelGGL(dc_level_kernel<LI_LIGHT>, dim3(workers), dim3(NT), lds_bytes,
                        (hipStream_t)stream, args);
   else if (inst == LI_RHS)
@@ -1411,6 +1688,7 @@ int dcx_level_setup(void) {
   for (const void *f : {(const void *)dc_level_kernel<LI_FULL>,
                         (const void *)dc_level_kernel<LI_LIGHT>,
                         (const void *)dc_level_kernel<LI_RHS>,
+                        (const void *)dc_level_kernel<LI_POTRF>,
                         (const void *)dc_queue_panel_kernel<LI_FULL>,
                         (const void *)dc_queue_panel_kernel<LI_LIGHT>,
                         (const void *)dc_queue_panel_kernel<LI_RHS>})
@@ -1457,7 +1735,9 @@ int dcx_queue_occupancy(size_t lds_bytes, int inst, int *blocks_per_cu) {
 int dcx_level_occupancy(size_t lds_bytes, int inst, int *blocks_per_cu) {
   int nb = 0;
   hipError_t e =
-      inst == LI_LIGHT ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+      inst == LI_POTRF ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                             &nb, dc_level_kernel<LI_POTRF>, NT, lds_bytes)
+      : inst == LI_LIGHT ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
                              &nb, dc_level_kernel<LI_LIGHT>, NT, lds_bytes)
       : inst == LI_RHS ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
                              &nb, dc_level_kernel<LI_RHS>, NT, lds_bytes)

@@ -42,8 +42,18 @@ __host__ __device__ inline int panel_stride(int nb) { return (nb + 31) / 32 * 32
 __host__ __device__ inline int trsm_lds_doubles(int nb) {
   return 2 * TRSM_ROWS * panel_stride(nb) + PANEL * (PANEL + 1);
 }
+// Largest tile order the register-resident POTRF takes (every 16x16 block
+// of its lower triangle held in MFMA accumulators across the four waves).
+constexpr int RPOTRF_MAX = 256;
 __host__ __device__ inline int potrf_lds_doubles(int nb) {
-  return PANEL * panel_stride(nb) + PANEL * (PANEL + 1) + 8;
+  // the larger of: the left-looking POTRF (any order; the full panel-kernel
+  // instance runs it), with the pivot rows left of the panel (16 x panel
+  // stride), the published pivot rows and a flag; and, up to RPOTRF_MAX, the
+  // register-resident one, with two panel buffers of nb (rounded to 16) rows
+  // of 17 doubles, the published pivot rows and a flag
+  const int left = PANEL * panel_stride(nb) + PANEL * (PANEL + 1) + 8;
+  const int regs = 2 * ((nb + 15) / 16 * 16) * (PANEL + 1) + PANEL * (PANEL + 1) + 8;
+  return nb <= RPOTRF_MAX && regs > left ? regs : left;
 }
 // Solve units (TRSM_L, TRSM_LT): the right-hand-side columns of the tile
 // (nb x 16, row stride BSS: 16 lanes reading one column of 16 different rows
@@ -59,7 +69,7 @@ constexpr int SOLVE_INV_ROWS = 16;
 // Rows of a right-hand-side update unit (GEMM_RHS_N, GEMM_RHS_T) and its LDS.
 constexpr int RHS_ROWS = 16;
 // instances of the level kernel
-constexpr int LI_FULL = 0, LI_LIGHT = 1, LI_RHS = 2;
+constexpr int LI_FULL = 0, LI_LIGHT = 1, LI_RHS = 2, LI_POTRF = 3;
 constexpr int RHS_LDS_DOUBLES = 16 * 16 * 8;
 constexpr int PANEL_LDS_DOUBLES = 2 * TRSM_ROWS * (MAX_TILE + 2) + PANEL * (PANEL + 1);
 
@@ -108,9 +118,9 @@ struct QueueArgs {
 }  // namespace dcx
 
 // Launches one level on `stream` (a hipStream_t); returns a hipError_t value.
-// inst: the instance of the level kernel (dcx::LI_FULL for any units,
-// LI_LIGHT for residual and elementwise units only, LI_RHS for solve
-// right-hand-side updates only).
+// inst: the instance of the level kernel (dcx::LI_FULL for any units but
+// POTRF, LI_LIGHT for residual and elementwise units only, LI_RHS for solve
+// right-hand-side updates only, LI_POTRF for POTRF units only).
 extern "C++" int dcx_launch_level(const dcx::LevelArgs &args, int workers, size_t lds_bytes,
                                   int inst, void *stream);
 // Allows the level kernel its largest dynamic LDS size.

@@ -899,6 +899,12 @@ static size_t lds_for(const TaskDesc &d) {
 // Fewest CUs the panel kernel gets next to the GEMM kernels (measured at
 // n = 32768, tile 512: 16 beats 0, 40, 64 and 96).
 constexpr int PANEL_MIN_CUS = 16;
+// item counters per level: other panel units, the three GEMM variants, POTRF
+constexpr int NCNT = 5;
+
+// POTRF tasks the POTRF instance of the panel kernel runs (the register-
+// resident factor; its instance has the registers for nothing else)
+static bool regs_potrf(const TaskDesc &d) { return d.kind == K_POTRF && d.m <= RPOTRF_MAX; }
 
 // Rough duration (ns) of a task on one CU, for balancing levels.
 static double cost_ns(const TaskDesc &d) {
@@ -909,7 +915,17 @@ static double cost_ns(const TaskDesc &d) {
     case K_TRSM: case K_TRSM_CAST: return m * n * n / 20.0;
     case K_TRTRI: return n * n * n / 28.0;
     case K_TRSM_INV: case K_TRSM_INV_CAST: return m * n * n / 50.0;
-    case K_POTRF: return m * m * m / 3.0 / 30.0 + 2000.0;
+    case K_POTRF:
+      if (d.m <= RPOTRF_MAX) {
+        // register-resident factor: a fixed cost per 16-column step plus the
+        // trailing MFMA updates (fit to single-tile durations, 20 us at 32,
+        // 88 us at 128, 219 us at 256)
+        const double mb = (m + 15.0) / 16.0;
+        return 9940.0 * mb + 14.6 * mb * mb * mb;
+      }
+      // left-looking factor: latency-bound, about quadratic (444 us at 257,
+      // 1.44 ms at 512)
+      return std::max(5.5 * m * m, m * m * m / 90.0) + 2000.0;
     case K_TRSM_L: case K_TRSM_LT: return m * m * 8.0 / 20.0 + 2000.0;
     case K_TRSM_L_INV: case K_TRSM_LT_INV: return m * m * 8.0 / 100.0 + 2000.0;
     case K_GEMM_RHS_N: case K_GEMM_RHS_T: return m * k * 8.0 / 50.0;
@@ -1286,8 +1302,8 @@ extern "C" int dc_flush(dc_runtime *rt) {
   // two-half kernel), then those with BF16 inputs
   auto is_g64 = [](const TaskDesc &d) { return d.ta == T_F64 || d.ta == T_F32; };
   std::vector<int64_t> pcount(nl, 0), gcount(nl, 0), lcount(nl, 0), g64count(nl, 0),
-      g32count(nl, 0);
-  std::vector<double> pcost(nl, 0.0), gcost(nl, 0.0);
+      g32count(nl, 0), potcount(nl, 0);
+  std::vector<double> pcost(nl, 0.0), gcost(nl, 0.0), potcost(nl, 0.0);
   const bool timing = rt->ktiming;
   std::vector<double> wflops(timing ? 2 * nl : 0, 0.0), wbytes(timing ? 2 * nl : 0, 0.0);
   // work items: one per unit, except FP64 GEMM/SYRK tasks, whose units are
@@ -1303,6 +1319,10 @@ extern "C" int dc_flush(dc_runtime *rt) {
     total_units += d.nunits;
     total_items += ni;
     (is_gemm(d) ? gcount : pcount)[level[t]] += ni;
+    if (regs_potrf(d)) {
+      potcount[level[t]] += ni;
+      potcost[level[t]] += cost_ns(d);
+    }
     if (paired(d)) (d.ta == T_F64 ? g64count : g32count)[level[t]] += ni;
     (is_gemm(d) ? gcost : pcost)[level[t]] += cost_ns(d);
     lcount[level[t]] += ni;
@@ -1321,7 +1341,7 @@ extern "C" int dc_flush(dc_runtime *rt) {
   auto take = [&](int64_t bytes) { int64_t o = off; off = align_up(off + bytes, 256); return o; };
   const int64_t o_desc = take(nt * (int64_t)sizeof(TaskDesc));
   const int64_t o_items = take(total_items * 8);
-  const int64_t o_cnt = take(4 * nl * 8);
+  const int64_t o_cnt = take(NCNT * nl * 8);
   const int64_t o_tail = off;
   const int64_t o_info = take(std::max(nslots_roots, 1) * 8);
   const int64_t o_failed = take(std::max(nslots_roots, 1) * 4);
@@ -1377,17 +1397,23 @@ extern "C" int dc_flush(dc_runtime *rt) {
     const double cy = cost_ns(rt->tasks[y].desc) / rt->tasks[y].desc.nunits;
     return cx > cy;
   });
-  // GEMM section of a level: FP64-input pairs, FP32-input pairs, BF16 units
-  std::vector<int64_t> fillp(lbegin), fillg(gbegin), fill32(nl), filll(nl);
+  // panel section of a level: POTRF units the register-resident factor
+  // takes (their own kernel instance), then the rest; GEMM section: FP64-input pairs, FP32-input pairs, BF16 units
+  std::vector<int64_t> fillpot(lbegin), fillp(nl), fillg(gbegin), fill32(nl), filll(nl);
   for (int64_t L = 0; L < nl; ++L) {
+    fillp[L] = lbegin[L] + potcount[L];
     fill32[L] = gbegin[L] + g64count[L];
     filll[L] = fill32[L] + g32count[L];
   }
-  std::vector<size_t> llds(nl, 16);
-  // levels whose panel units are all residual or elementwise work run the
-  // light instance of the panel kernel, levels of solve right-hand-side
-  // updates only the RHS instance (both four workgroups per CU: these units
-  // stream from memory); any other level the full instance
+  std::vector<size_t> llds(nl, 16), lpot(nl, 16);
+  // POTRF units of order <= RPOTRF_MAX run the POTRF instance of the panel
+  // kernel (larger ones the full instance: a third concurrent kernel per
+  // level cost 8% at n = 32768, tile 512, with no faster factor to show for
+  // it); of the other
+  // panel units, those of a level that are all residual or elementwise work
+  // run the light instance, all solve right-hand-side updates the RHS
+  // instance (both four workgroups per CU: these units stream from memory),
+  // any others the full instance
   auto light_kind = [](int kind) {
     return kind == K_SCAL || kind == K_CAST || kind == K_RESID || kind == K_AXPY;
   };
@@ -1399,17 +1425,20 @@ extern "C" int dc_flush(dc_runtime *rt) {
     desc[t] = k.desc;
     const int L = level[t];
     const bool g = is_gemm(k.desc);
-    if (!g) llds[L] = std::max(llds[L], lds_for(k.desc));
-    if (!g && !light_kind(k.desc.kind)) llight[L] = 0;
-    if (!g && !rhs_kind(k.desc.kind)) lrhs[L] = 0;
-    int64_t &fp = !g ? fillp[L]
+    const bool pot = regs_potrf(k.desc);
+    if (pot) lpot[L] = std::max(lpot[L], lds_for(k.desc));
+    else if (!g) llds[L] = std::max(llds[L], lds_for(k.desc));
+    if (!g && !pot && !light_kind(k.desc.kind)) llight[L] = 0;
+    if (!g && !pot && !rhs_kind(k.desc.kind)) lrhs[L] = 0;
+    int64_t &fp = pot ? fillpot[L]
+                  : !g ? fillp[L]
                   : !is_g64(k.desc) ? filll[L]
                   : k.desc.ta == T_F64 ? fillg[L] : fill32[L];
     const int step = paired(k.desc) ? 2 : 1;
     for (int u = 0; u < k.desc.nunits; u += step)
       items[fp++] = ((uint64_t)(uint32_t)t << 32) | (uint32_t)u;
   }
-  memset(hb + o_cnt, 0, 4 * nl * 8);
+  memset(hb + o_cnt, 0, NCNT * nl * 8);
   memset(hb + o_info, 0, std::max(nslots_roots, 1) * 8);
   memset(hb + o_failed, 0, std::max(nslots_roots, 1) * 4);
   if (trace) {
@@ -1442,11 +1471,12 @@ extern "C" int dc_flush(dc_runtime *rt) {
     a.info = (int64_t *)(db + o_info);
     a.trace = trace ? (int64_t *)(db + o_trace) : nullptr;
     const bool hasp = pcount[L] > 0, hasg = gcount[L] > 0;
+    const int64_t npot = potcount[L], nrest = pcount[L] - npot;
     const int cus = rt->cfg.workers > 0 ? rt->cfg.workers : rt->num_cus;
-    int pworkers = 0, pcus = 0;
+    int pworkers = 0, potworkers = 0, pcus = 0;
     if (hasp) {
       int per_cu = 1;
-      dcx_level_occupancy(llds[L], linst(L), &per_cu);
+      if (nrest > 0) dcx_level_occupancy(llds[L], linst(L), &per_cu);
       pcus = cus;
       if (hasg) {
         // CUs shared in proportion to the estimated work of the two kernels,
@@ -1461,8 +1491,21 @@ extern "C" int dc_flush(dc_runtime *rt) {
         pcus = std::min(std::max({1, (int)std::ceil(share * cus), floor_cus}),
                         std::max(1, cus - 1));
       }
-      pworkers = (int)std::max<int64_t>(
-          1, std::min<int64_t>(pcount[L], (int64_t)pcus * std::max(1, per_cu)));
+      // the POTRF instance (a whole CU per workgroup) and the other panel
+      // units split the panel's CUs in proportion to their estimated work,
+      // each getting at least one
+      int potcus = 0;
+      if (npot > 0)
+        potcus = nrest == 0 ? pcus
+                            : std::min(std::max(1, (int)std::lround(
+                                                       pcus * potcost[L] / std::max(1.0, pcost[L]))),
+                                       std::max(1, pcus - 1));
+      potworkers = (int)std::min<int64_t>(npot, potcus);
+      if (nrest > 0) {
+        const int rest_cus = std::max(1, pcus - potworkers);
+        pworkers = (int)std::max<int64_t>(
+            1, std::min<int64_t>(nrest, (int64_t)rest_cus * std::max(1, per_cu)));
+      }
     }
     // CUs left to the GEMM kernels.  Both take one workgroup per CU (a
     // whole CU's LDS or registers), so launching gcus of them leaves pcus
@@ -1473,22 +1516,59 @@ extern "C" int dc_flush(dc_runtime *rt) {
     hipStream_t pstream = rt->stream;
     // with fixed buffers both kernels of a level run on the runtime's
     // stream, one after the other (no events to create)
-    hipEvent_t join = nullptr;
-    if (hasp && hasg && !ext) {
-      // fork: the panel units run on the side stream next to the GEMM units
+    hipStream_t potstream = rt->stream;
+    hipEvent_t join = nullptr, join2 = nullptr;
+    // up to three kernels of a level run side by side: POTRF units, other
+    // panel units and GEMM units; the first on the runtime's stream, the
+    // others forked onto side streams (with fixed buffers all run on the
+    // runtime's stream, one after the other: no events to create)
+    const int nkern = (npot > 0) + (nrest > 0) + hasg;
+    if (nkern > 1 && !ext) {
+      if (rt->side2 == nullptr) {
+        const int er = ensure_stream(&rt->side2);
+        if (er) return fail(er);
+      }
       hipEvent_t fork = take_event(rt, false);
       if (fork) f.evs.push_back(fork);
       join = take_event(rt, false);
       if (join) f.evs.push_back(join);
-      if (!fork || !join) return fail(-EIO);
+      if (nkern > 2) {
+        join2 = take_event(rt, false);
+        if (join2) f.evs.push_back(join2);
+      }
+      if (!fork || !join || (nkern > 2 && !join2)) return fail(-EIO);
       hipEventRecord(fork, rt->stream);
       hipStreamWaitEvent(rt->side, fork, 0);
-      pstream = rt->side;
+      if (nkern > 2) hipStreamWaitEvent(rt->side2, fork, 0);
+      // GEMM units keep the runtime's stream; of the panel kernels, the
+      // POTRF one goes to side2 when the other panel kernel also runs
+      if (hasg) {
+        pstream = rt->side;
+        potstream = nrest > 0 ? rt->side2 : rt->side;
+      } else {
+        potstream = rt->side;
+      }
     }
-    if (hasp) {
+    if (npot > 0) {
       a.begin = lbegin[L];
-      a.count = pcount[L];
-      a.counter = (unsigned long long *)(db + o_cnt) + 4 * L;
+      a.count = npot;
+      a.counter = (unsigned long long *)(db + o_cnt) + NCNT * L + 4;
+      hipEvent_t tb = timing ? tev(potstream) : nullptr;
+      int le = dcx_launch_level(a, std::max(1, potworkers), lpot[L], LI_POTRF, potstream);
+      if (le != 0) return fail(fail_hip((hipError_t)le, "level launch"));
+      if (timing) {
+        hipEvent_t te = tev(potstream);
+        if (!tb || !te) return fail(-EIO);
+        // the level's panel work is credited to its other panel launch when
+        // there is one
+        f.timed.push_back({tb, te, 0, nrest > 0 ? 0.0 : wflops[2 * L],
+                           nrest > 0 ? 0.0 : wbytes[2 * L]});
+      }
+    }
+    if (nrest > 0) {
+      a.begin = lbegin[L] + npot;
+      a.count = nrest;
+      a.counter = (unsigned long long *)(db + o_cnt) + NCNT * L;
       hipEvent_t tb = timing ? tev(pstream) : nullptr;
       int le = dcx_launch_level(a, pworkers, llds[L], linst(L), pstream);
       if (le != 0) return fail(fail_hip((hipError_t)le, "level launch"));
@@ -1507,7 +1587,7 @@ extern "C" int dc_flush(dc_runtime *rt) {
         if (cnt > 0) {
           a.begin = begin;
           a.count = cnt;
-          a.counter = (unsigned long long *)(db + o_cnt) + 4 * L + 1 + v;
+          a.counter = (unsigned long long *)(db + o_cnt) + NCNT * L + 1 + v;
           const int wg = (int)std::min<int64_t>(cnt, gcus);
           gworkers = std::max(gworkers, wg);
           const int le = v < 2 ? dcx_launch_gemm(a, wg, v == 0 ? T_F64 : T_F32, rt->stream)
@@ -1526,7 +1606,11 @@ extern "C" int dc_flush(dc_runtime *rt) {
       hipEventRecord(join, rt->side);
       hipStreamWaitEvent(rt->stream, join, 0);
     }
-    max_workers = std::max(max_workers, pworkers + gworkers);
+    if (join2) {
+      hipEventRecord(join2, rt->side2);
+      hipStreamWaitEvent(rt->stream, join2, 0);
+    }
+    max_workers = std::max(max_workers, potworkers + pworkers + gworkers);
   }
   f.arena_dev = arena_dev;
   f.tail_off = o_tail;

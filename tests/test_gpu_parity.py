@@ -257,7 +257,7 @@ def test_trsm_inv_cast_writes_bf16_copy(dc, rt, torch_dev):
     assert np.abs(got.numpy().astype(np.float64) - ref).max() <= tol * np.abs(ref).max()
 
 
-@pytest.mark.parametrize("nb", [1, 16, 37, 128, 512])
+@pytest.mark.parametrize("nb", [1, 16, 37, 100, 128, 200, 255, 256, 257, 512])
 def test_potrf_task(dc, rt, torch_dev, nb):
     a = inputs.spd_normal(nb, nb, 0.1)
     got = _single(dc, rt, dc.DC_POTRF, [a], [dc.DC_RW], torch_dev)[0]
@@ -325,6 +325,23 @@ def test_breakdown_info(dc, rt, torch_dev):
     a2[0, 0] = -1.0
     _, info2, _ = _factor(dc, rt, torch_dev, a2, 32)
     assert info2 == 1
+
+
+@pytest.mark.parametrize("nb", [40, 200, 256, 300])
+def test_potrf_tile_breakdown_column(dc, rt, torch_dev, nb):
+    """One tile (one POTRF task): a pivot made negative at column p gives
+    info p + 1, at the first column, inside a 16-column block, at block
+    edges and at the last column; the finished block columns left of p's
+    block are exact (integer factor)."""
+    a, l0 = inputs.integer_factor(nb, nb + 3)
+    for p in sorted({0, 15, 16, 17, nb // 2 + 5, nb - 1}):
+        a2 = a.copy()
+        a2[p, p] -= 1e7
+        l, info, _ = _factor(dc, rt, torch_dev, a2, nb)
+        assert info == p + 1, (p, info)
+        assert core.potrf_tiled(a2, nb)[1] == p + 1
+        done = 16 * (p // 16)
+        assert np.array_equal(l[:, :done], l0[:, :done]), p
 
 
 def test_deterministic_across_runs_and_workers(dc, torch_dev):
