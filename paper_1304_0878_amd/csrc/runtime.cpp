@@ -792,8 +792,25 @@ static int retire(dc_runtime *rt, Inflight &f) {
     if (e != hipSuccess) {
       status = fail_hip(e, "hipMemcpy(trace)");
     } else {
+      if (!f.xfirst.empty()) {
+        // a split task spans its sub-tasks; the last one names the worker
+        const int64_t ns = (int64_t)f.xfirst.size() - 1;
+        std::vector<int64_t> tr(3 * ns);
+        for (int64_t t = 0; t < ns; ++t) {
+          int64_t s = INT64_MAX, e2 = 0, w = -1;
+          for (int64_t x = f.xfirst[t]; x < f.xfirst[t + 1]; ++x) {
+            s = std::min(s, rt->trace_host[3 * x]);
+            e2 = std::max(e2, rt->trace_host[3 * x + 1]);
+            w = rt->trace_host[3 * x + 2];
+          }
+          tr[3 * t] = s;
+          tr[3 * t + 1] = e2;
+          tr[3 * t + 2] = w;
+        }
+        rt->trace_host.swap(tr);
+      }
       rt->trace_t0 = INT64_MAX;
-      for (int64_t t = 0; t < f.ntasks; ++t)
+      for (size_t t = 0; t < rt->trace_host.size() / 3; ++t)
         rt->trace_t0 = std::min(rt->trace_t0, rt->trace_host[3 * t]);
       rt->trace_kind = f.kinds;
     }
@@ -1271,6 +1288,98 @@ static int flush_queue(dc_runtime *rt, std::chrono::steady_clock::time_point t_b
   return 0;
 }
 
+// POTRF tasks on FP64 tiles of order in (RPOTRF_MAX, 2 RPOTRF_MAX] are laid
+// out as the blocked factorisation of the tile, four tasks on its sub-blocks
+// (order h = RPOTRF_MAX, then the rest): POTRF(A11); TRSM(A11, A21);
+// SYRK(A21, A22); POTRF(A22).  Both diagonal blocks then take the
+// register-resident factor, and the two off-diagonal tasks spread over CUs.
+// The first sub-task takes the task's predecessors, each next one depends on
+// the one before, and the task's successors depend on the last.  The
+// submitted graph is unchanged for the caller: the trace reports each task
+// over its sub-tasks.
+//
+// A split only pays where the factor is the long pole of its level: next to
+// a level's worth of other work (the GEMMs of an early step of a large
+// factorisation, or the other factors of a batch) the task's latency is
+// hidden and the three extra levels only add launch gaps.  So levels are
+// first assigned to the graph as submitted, and a task is split when its
+// estimated duration exceeds 1.5 times its level's estimated work spread
+// over the CUs.  Returns the first laid-out task of every submitted task
+// (and the total), or nothing when no task is split.
+static std::vector<int64_t> split_potrf(dc_runtime *rt, int workers) {
+  auto candidate = [](const TaskDesc &d) {
+    return d.kind == K_POTRF && d.tc == T_F64 && d.m > RPOTRF_MAX && d.m <= 2 * RPOTRF_MAX;
+  };
+  int64_t ncand = 0;
+  for (const Task &t : rt->tasks) ncand += candidate(t.desc);
+  if (ncand == 0) return {};
+  std::vector<int32_t> level;
+  const int64_t nl = assign_levels(rt, workers, level);
+  std::vector<double> lwork(nl, 0.0);
+  for (size_t t = 0; t < rt->tasks.size(); ++t) lwork[level[t]] += cost_ns(rt->tasks[t].desc);
+  std::vector<char> split(rt->tasks.size(), 0);
+  int64_t nsplit = 0;
+  for (size_t t = 0; t < rt->tasks.size(); ++t) {
+    const TaskDesc &d = rt->tasks[t].desc;
+    if (candidate(d) && cost_ns(d) > 1.5 * lwork[level[t]] / std::max(1, workers)) {
+      split[t] = 1;
+      ++nsplit;
+    }
+  }
+  if (nsplit == 0) return {};
+  const int64_t nt = (int64_t)rt->tasks.size();
+  std::vector<int64_t> first(nt + 1, 0);
+  std::vector<Task> out;
+  out.reserve(nt + 3 * nsplit);
+  for (int64_t t = 0; t < nt; ++t) {
+    Task &k = rt->tasks[t];
+    first[t] = (int64_t)out.size();
+    // a predecessor's successors wait for its last laid-out task
+    for (int64_t &p : k.preds) p = first[p + 1] - 1;
+    if (!split[t]) {
+      out.push_back(std::move(k));
+      continue;
+    }
+    const TaskDesc d = k.desc;
+    const int h = RPOTRF_MAX, m2 = d.m - RPOTRF_MAX;
+    const int64_t ld = d.ldc;
+    auto blk = [&](int64_t r, int64_t c) { return (void *)((char *)d.c + (r * ld + c) * 8); };
+    TaskDesc sub[4];
+    memset(sub, 0, sizeof(sub));
+    sub[0] = d;
+    sub[0].m = h;
+    sub[1].kind = K_TRSM;
+    sub[1].m = m2; sub[1].n = h;
+    sub[1].a = d.c; sub[1].lda = ld; sub[1].ta = T_F64;
+    sub[1].c = blk(h, 0); sub[1].ldc = ld; sub[1].tc = T_F64;
+    sub[2].kind = K_SYRK;
+    sub[2].m = m2; sub[2].k = h;
+    sub[2].a = blk(h, 0); sub[2].lda = ld; sub[2].ta = T_F64;
+    sub[2].c = blk(h, h); sub[2].ldc = ld; sub[2].tc = T_F64;
+    sub[3] = d;
+    sub[3].m = m2;
+    sub[3].c = blk(h, h);
+    sub[3].row0 = d.row0 + h;
+    for (int i = 0; i < 4; ++i) {
+      sub[i].matrix = d.matrix;
+      sub[i].nunits = units_for(sub[i]);
+      Task x;
+      x.desc = sub[i];
+      x.prio = k.prio;
+      if (i == 0) {
+        x.preds = k.preds;
+        x.nwar = k.nwar;
+      } else {
+        x.preds = {(int64_t)out.size() - 1};
+      }
+      out.push_back(std::move(x));
+    }
+  }
+  first[nt] = (int64_t)out.size();
+  rt->tasks.swap(out);
+  return first;
+}
+
 extern "C" int dc_flush(dc_runtime *rt) {
   if (!rt) return -EINVAL;
   if (rt->tasks.empty()) return 0;
@@ -1291,8 +1400,12 @@ extern "C" int dc_flush(dc_runtime *rt) {
     drop();
     return err;
   }
-  const int64_t nt = (int64_t)rt->tasks.size();
+  // submitted kinds, before any task is split
+  std::vector<int32_t> kinds_sub(rt->tasks.size());
+  for (size_t t = 0; t < rt->tasks.size(); ++t) kinds_sub[t] = rt->tasks[t].desc.kind;
   const int workers_cfg = rt->cfg.workers > 0 ? rt->cfg.workers : rt->num_cus;
+  std::vector<int64_t> xfirst = split_potrf(rt, workers_cfg);
+  const int64_t nt = (int64_t)rt->tasks.size();
   std::vector<int32_t> level;
   const int64_t nl = assign_levels(rt, workers_cfg, level);
   // per level: panel-kernel units first, then GEMM/SYRK units
@@ -1619,10 +1732,10 @@ extern "C" int dc_flush(dc_runtime *rt) {
   f.info_off = o_info;
   f.trace_off = o_trace;
   f.ntasks = nt;
+  f.xfirst = std::move(xfirst);
   f.slot_roots = rt->slot_roots;
   f.slot_factor = rt->slot_factor;
-  f.kinds.resize(nt);
-  for (int64_t t = 0; t < nt; ++t) f.kinds[t] = rt->tasks[t].desc.kind;
+  f.kinds = std::move(kinds_sub);
   f.handles = rt->touched;
   err = enqueue_graph(rt, std::move(f));
   if (err) return fail(err);

@@ -83,10 +83,13 @@ struct Inflight {
   void *arena_dev = nullptr;       // where the graph's layout lives
   int arena = -1;                  // index in dc_runtime::arenas, -1 for fixed buffers
   int64_t tail_off = 0, tail_bytes = 0, status_off = 0, info_off = 0, trace_off = 0;
-  int64_t ntasks = 0;
+  int64_t ntasks = 0;               // tasks laid out (after splitting)
+  // first laid-out task of each submitted task (and the total) when some
+  // tasks were split, else empty
+  std::vector<int64_t> xfirst;
   std::vector<dc_handle> slot_roots;
   std::vector<char> slot_factor;   // slot has a POTRF task in the graph
-  std::vector<int32_t> kinds;
+  std::vector<int32_t> kinds;       // per submitted task
   std::vector<dc_handle> handles;  // handles the flushed graph references
   hipEvent_t done = nullptr;       // recorded after the graph's last launch
   std::vector<hipEvent_t> evs;     // its fork/join events
