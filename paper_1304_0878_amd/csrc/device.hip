@@ -494,47 +494,80 @@ __device__ __forceinline__ void run_trsm_inv(const TaskDesc &d, int unit, double
 //
 // Register-resident POTRF of a diagonal tile of order nb <= RPOTRF_MAX.  The
 // lower triangle is cut into 16x16 blocks (I, J), J <= I, of MB block rows.
-// Block column 0 goes from memory straight to LDS; the blocks with J >= 1,
-// numbered column by column from (1, 1), live in MFMA accumulators: block b
-// in slot b / 4 of wave b % 4 (lane l holds rows 16I + l/16 + 4e, e = 0..3,
-// of column 16J + l%16: the result layout of v_mfma_f64_16x16x4f64).
-// Right-looking over the block columns k:
-//  (1) the blocks of column k are published to LDS;
-//  (2) the first wave factors the diagonal block in registers, lane i
+// Block column 0 goes from memory straight to LDS; the blocks with J >= 1
+// live in MFMA accumulators (lane l holds rows 16I + l/16 + 4e, e = 0..3, of
+// column 16J + l%16: the result layout of v_mfma_f64_16x16x4f64).  Wave w
+// holds block rows w, 7 - w, 8 + w and 15 - w: the first two have 7 blocks
+// with J >= 1 between them and the last two 23, for every w, so each wave
+// has 30 slots, and slot s maps to its block with one comparison
+// (rp_slot).
+// Right-looking over the block columns k (the blocks of column k are in LDS
+// when step k starts: column 0 from memory, column k + 1 published by the
+// update of step k, which finishes it):
+//  (1) the first wave factors the diagonal block in registers, lane i
 //      holding row i: for each column j the pivot is taken from lane j, its
-//      square root and reciprocal are formed once, column j is scaled, and
+//      reciprocal square root r is formed once (hardware estimate and two
+//      Newton steps) with l_jj = pivot * r, column j is scaled by r, and
 //      the columns right of it take a rank-one update whose column-j entries
 //      come from their lanes (readlane); the block is stored, and published
-//      with the reciprocals of its diagonal for step (3);
-//  (3) every thread takes one row below the diagonal block and solves it by
+//      with the reciprocals of its diagonal for step (2);
+//  (2) every thread takes one row below the diagonal block and solves it by
 //      substitution in the same column order (multiplying by the published
 //      reciprocals), then stores and publishes it;
-//  (4) each wave subtracts P_I P_J^T from its blocks right of column k with
-//      four MFMAs (K = 16), reading the next block's operands before the
-//      current block's products.
+//  (3) each wave subtracts P_I P_J^T from its blocks right of column k with
+//      four MFMAs (K = 16), RP_UGROUP slots at a time: a group with no block
+//      right of column k is skipped, otherwise the operands of its slots are
+//      read and their MFMA chains interleaved (a group may run a slot whose
+//      block is finished or outside the tile: its accumulator is never read
+//      again, and its operand rows are clamped into the buffer); the
+//      group's blocks of column k + 1, now final, are published to the
+//      other panel buffer for step k + 1.
 // Rows and columns beyond nb are padded with the identity, which factors to
 // itself and leaves the real entries unchanged.  Returns 0, or the 1-based
 // column (within the tile) of the first non-positive or NaN pivot; the block
 // columns left of that pivot's block hold their final values.
 constexpr int RP_MB = RPOTRF_MAX / 16;
 constexpr int RP_SLOTS = (RP_MB * (RP_MB - 1) / 2 + 3) / 4;   // 30
+static_assert(RP_MB == 16 && RP_SLOTS == 30, "the row pairing of rp_slot assumes 16 block rows");
 constexpr int RP_LD = PANEL + 1;                              // 17
-constexpr int RP_GROUP = 6;                                  // slots loaded together
+constexpr int RP_LDT = PANEL + 2;                             // 18
+constexpr int RP_GROUP = 6;                                   // slots loaded together
+constexpr int RP_UGROUP = 4;                                  // slots updated together
 
 typedef double dvec4 __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ dvec4 mfma16(double a, double b, dvec4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-// Moves (I, J) forward by `step` blocks in the column-by-column numbering of
-// the lower triangle of MB block rows; J == MB once past the last block.
-// Every argument is wave-uniform, so this is scalar arithmetic.
-__device__ __forceinline__ void rp_advance(int &I, int &J, int step, int MB) {
-  I += step;
-  while (J < MB && I >= MB) {
-    I = I - MB + J + 1;
-    J += 1;
+// Block (I, J) of slot s of wave w (both wave-uniform, s a constant after
+// unrolling): slots 0..6 run along rows w (J = 1..w) then 7 - w, slots 7..29
+// along rows 8 + w then 15 - w.  The block exists in a tile of MB block rows
+// when I < MB.
+__device__ __forceinline__ void rp_slot(int s, int w, int &I, int &J) {
+  if (s < 7) {
+    const bool first = s < w;
+    I = first ? w : 7 - w;
+    J = first ? 1 + s : 1 + s - w;
+  } else {
+    const int t = s - 7;
+    const bool first = t < 8 + w;
+    I = first ? 8 + w : 15 - w;
+    J = first ? 1 + t : 1 + t - 8 - w;
   }
+}
+
+// 1 / sqrt(x) for a positive normal x: the hardware estimate refined by two
+// Newton steps, r <- r + r (1 - x r^2) / 2 (quadratic convergence from the
+// estimate's relative error, well below 2^-20, to rounding level; exact for
+// powers of four).
+__device__ __forceinline__ double rsqrt_nr(double x) {
+  double r = __builtin_amdgcn_rsq(x);
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    const double e = fma(-x * r, r, 1.0);
+    r = fma(0.5 * r, e, r);
+  }
+  return r;
 }
 
 template <typename TS>
@@ -551,82 +584,80 @@ __device__ __forceinline__ int run_potrf_regs(const TaskDesc &d, double *lds) {
   // two panel buffers of npad rows (step k uses buffer k % 2; addresses are
   // formed from lds so that they stay LDS addresses)
   const int pbuf = npad * RP_LD;
-  // pivot block: row i of L_kk in Ds[i][0..i], 1 / l_ii in Ds[i][16]
-  double *Ds = lds + 2 * pbuf;
-  int *flag = (int *)(Ds + PANEL * (PANEL + 1));
-  // first slot of this wave: block w of the numbering from (1, 1)
-  int I0 = 1, J0 = 1;
-  rp_advance(I0, J0, w, MB);
+  // pivot block, transposed: l_pj in Lt[j][p] (zero above the diagonal),
+  // with an even stride so that column j is read in aligned pairs; 1 / l_jj
+  // in Rinv[j]
+  double *Lt = lds + 2 * pbuf;
+  double *Rinv = Lt + PANEL * RP_LDT;
+  int *flag = (int *)(Rinv + PANEL);
 
   // block column 0 into the first panel buffer (identity padding): thread t
-  // takes elements t, t + NT, ..., four loads (clamped in bounds) issued
-  // before their LDS writes
-  {
-    constexpr int PER = RPOTRF_MAX * PANEL / NT;   // 16
+  // copies row t, its 16 loads (indices clamped in bounds) issued together
+  if (tid < npad) {
+    const int row = tid;
+    const int64_t roff = (int64_t)min(row, nb - 1) * ldd;
+    double v[PANEL];
 #pragma unroll
-    for (int q0 = 0; q0 < PER; q0 += 4) {
-      double v[4];
+    for (int c = 0; c < PANEL; ++c) v[c] = (double)D[roff + min(c, nb - 1)];
+    // every load issued before the first use (left to itself the scheduler
+    // puts each use, and a wait, right after its load)
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int idx = tid + (q0 + q) * NT, row = idx >> 4, col = idx & 15;
-        v[q] = (double)D[(int64_t)min(row, nb - 1) * ldd + min(col, nb - 1)];
-      }
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int idx = tid + (q0 + q) * NT, row = idx >> 4, col = idx & 15;
-        if (row < npad)
-          lds[row * RP_LD + col] =
-              row < nb && col < nb && col <= row ? v[q] : (row == col ? 1.0 : 0.0);
-      }
-      if ((q0 + 4) * NT >= npad * PANEL) break;
-    }
+    for (int c = 0; c < PANEL; ++c)
+      lds[row * RP_LD + c] = row < nb && c < nb && c <= row ? v[c] : (row == c ? 1.0 : 0.0);
   }
   // the other blocks into the accumulators, RP_GROUP slots at a time: every
   // element read is in bounds (indices clamped), so a group's loads carry no
   // branches and issue back to back
   dvec4 acc[RP_SLOTS];
-  {
-    int I = I0, J = J0;
 #pragma unroll
-    for (int g = 0; g < RP_SLOTS; g += RP_GROUP) {
-      if (J < MB) {
+  for (int g = 0; g < RP_SLOTS; g += RP_GROUP) {
+    bool any = false;
 #pragma unroll
-        for (int s = g; s < g + RP_GROUP && s < RP_SLOTS; ++s) {
-          const bool valid = J < MB;
-          const int col = 16 * J + l16;
-          const int colc = min(col, nb - 1);
+    for (int s = g; s < g + RP_GROUP && s < RP_SLOTS; ++s) {
+      int I, J;
+      rp_slot(s, w, I, J);
+      any |= I < MB;
+    }
+    if (any) {
+      double v[RP_GROUP][4];
 #pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            const int row = 16 * I + kq + 4 * e;
-            const double v = (double)D[(int64_t)min(row, nb - 1) * ldd + colc];
-            acc[s][e] = valid && row < nb && col < nb && col <= row ? v : (row == col ? 1.0 : 0.0);
-          }
-          rp_advance(I, J, 4, MB);
-        }
-      } else {
+      for (int s = g; s < g + RP_GROUP && s < RP_SLOTS; ++s) {
+        int I, J;
+        rp_slot(s, w, I, J);
+        const int colc = min(16 * J + l16, nb - 1);
 #pragma unroll
-        for (int s = g; s < g + RP_GROUP && s < RP_SLOTS; ++s) acc[s] = (dvec4){0.0, 0.0, 0.0, 0.0};
+        for (int e = 0; e < 4; ++e)
+          v[s - g][e] = (double)D[(int64_t)min(16 * I + kq + 4 * e, nb - 1) * ldd + colc];
       }
+      // the group's loads all issued before the first use
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int s = g; s < g + RP_GROUP && s < RP_SLOTS; ++s) {
+        int I, J;
+        rp_slot(s, w, I, J);
+        const bool valid = I < MB;
+        const int col = 16 * J + l16;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int row = 16 * I + kq + 4 * e;
+          acc[s][e] = valid && row < nb && col < nb && col <= row ? v[s - g][e]
+                                                                  : (row == col ? 1.0 : 0.0);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int s = g; s < g + RP_GROUP && s < RP_SLOTS; ++s) acc[s] = (dvec4){0.0, 0.0, 0.0, 0.0};
     }
   }
 
   int bad = 0;
   for (int k = 0; k < MB; ++k) {
     double *Pk = lds + (k & 1) * pbuf;
-    // (1) publish block column k (block rows k .. MB - 1) to LDS
-    if (k > 0) {
-      int I = I0, J = J0;
-#pragma unroll
-      for (int s = 0; s < RP_SLOTS; ++s) {
-        if (J == k) {
-#pragma unroll
-          for (int e = 0; e < 4; ++e) Pk[(16 * I + kq + 4 * e) * RP_LD + l16] = acc[s][e];
-        }
-        rp_advance(I, J, 4, MB);
-      }
-    }
+    // block column k (block rows k .. MB - 1) is in Pk once every wave has
+    // finished the previous step
     __syncthreads();
-    // (2) the first wave factors the diagonal block; lane i holds row i
+    // (1) the first wave factors the diagonal block; lane i holds row i
     // (lanes 16..63 repeat rows 0..15 and store nothing)
     if (w == 0) {
       const int i = l16;
@@ -641,8 +672,8 @@ __device__ __forceinline__ int run_potrf_regs(const TaskDesc &d, double *lds) {
       for (int j = 0; j < PANEL; ++j) {
         const double piv = readlane_f64(v[j], j);
         if (!(piv > 0.0) && f == 0) f = j + 1;   // non-positive or NaN: uniform
-        const double djj = sqrt(piv);
-        const double rj = 1.0 / djj;
+        const double rj = rsqrt_nr(piv);
+        const double djj = piv * rj;
         v[j] = i == j ? djj : v[j] * rj;
         if (i == j) rinv = rj;
         // rank-one update of the columns right of j (entries above the
@@ -658,10 +689,10 @@ __device__ __forceinline__ int run_potrf_regs(const TaskDesc &d, double *lds) {
 #pragma unroll
         for (int j = 0; j < PANEL; ++j) {
           const double x = j <= i ? v[j] : 0.0;
-          Ds[i * RP_LD + j] = x;
+          Lt[j * RP_LDT + i] = x;
           if (j <= i && row < nb) D[(int64_t)row * ldd + 16 * k + j] = (TS)x;
         }
-        Ds[i * RP_LD + PANEL] = rinv;
+        Rinv[i] = rinv;
       }
       if (lane == 0) *flag = f;
     }
@@ -674,7 +705,7 @@ __device__ __forceinline__ int run_potrf_regs(const TaskDesc &d, double *lds) {
         break;
       }
     }
-    // (3) rows below the diagonal block, one per thread, by substitution
+    // (2) rows below the diagonal block, one per thread, by substitution
     // with the published factor
     {
       const int row = 16 * (k + 1) + tid;
@@ -682,11 +713,28 @@ __device__ __forceinline__ int run_potrf_regs(const TaskDesc &d, double *lds) {
         double x[PANEL];
 #pragma unroll
         for (int j = 0; j < PANEL; ++j) x[j] = Pk[row * RP_LD + j];
+        // column j of the pivot block and 1 / l_jj are read while column
+        // j - 1 is applied (left to itself the scheduler waits for each
+        // read right after issuing it)
+        double cur[PANEL], nxt[PANEL];
+        cur[0] = Rinv[0];
+#pragma unroll
+        for (int p = 1; p < PANEL; ++p) cur[p] = Lt[p];
 #pragma unroll
         for (int j = 0; j < PANEL; ++j) {
-          x[j] *= Ds[j * RP_LD + PANEL];
+          if (j + 1 < PANEL) {
+            nxt[0] = Rinv[j + 1];
 #pragma unroll
-          for (int p = j + 1; p < PANEL; ++p) x[p] = fma(-x[j], Ds[p * RP_LD + j], x[p]);
+            for (int p = j + 2; p < PANEL; ++p) nxt[p] = Lt[(j + 1) * RP_LDT + p];
+          }
+          __builtin_amdgcn_sched_barrier(0);
+          x[j] *= cur[0];
+#pragma unroll
+          for (int p = j + 1; p < PANEL; ++p) x[p] = fma(-x[j], cur[p], x[p]);
+          __builtin_amdgcn_sched_barrier(0);
+          cur[0] = nxt[0];
+#pragma unroll
+          for (int p = j + 2; p < PANEL; ++p) cur[p] = nxt[p];
         }
 #pragma unroll
         for (int j = 0; j < PANEL; ++j) Pk[row * RP_LD + j] = x[j];
@@ -703,45 +751,46 @@ __device__ __forceinline__ int run_potrf_regs(const TaskDesc &d, double *lds) {
       }
     }
     __syncthreads();
-    // (4) trailing update of this wave's blocks right of column k; the
-    // operands of the next live slot are read before the current slot's
-    // MFMAs (slots are numbered column by column, so the live ones, J > k,
-    // are the last valid ones)
-    {
-      int I = I0, J = J0;
-      auto rowa = [&](int Ib) { return (16 * Ib + l16) * RP_LD + kq; };
-      double an[4] = {0.0, 0.0, 0.0, 0.0}, bn[4] = {0.0, 0.0, 0.0, 0.0};
-      if (J < MB && J > k) {
+    // (3) trailing update of this wave's blocks right of column k
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          an[q] = Pk[rowa(I) + 4 * q];
-          bn[q] = Pk[rowa(J) + 4 * q];
-        }
+    for (int g = 0; g < RP_SLOTS; g += RP_UGROUP) {
+      const int gl = min(g + RP_UGROUP, RP_SLOTS) - 1;
+      bool any = false;
+#pragma unroll
+      for (int s = g; s <= gl; ++s) {
+        int I, J;
+        rp_slot(s, w, I, J);
+        any |= I < MB && J > k;
       }
+      if (any) {
+        double a[RP_UGROUP][4], b[RP_UGROUP][4];
 #pragma unroll
-      for (int s = 0; s < RP_SLOTS; ++s) {
-        double a[4], b[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          a[q] = an[q];
-          b[q] = bn[q];
-        }
-        const bool live = J < MB && J > k;
-        int I2 = I, J2 = J;
-        rp_advance(I2, J2, 4, MB);
-        if (s + 1 < RP_SLOTS && J2 < MB && J2 > k) {
+        for (int s = g; s <= gl; ++s) {
+          int I, J;
+          rp_slot(s, w, I, J);
+          const int ra = (16 * min(I, MB - 1) + l16) * RP_LD + kq;
+          const int rb = (16 * min(J, MB - 1) + l16) * RP_LD + kq;
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
-            an[q] = Pk[rowa(I2) + 4 * q];
-            bn[q] = Pk[rowa(J2) + 4 * q];
+            a[s - g][q] = -Pk[ra + 4 * q];
+            b[s - g][q] = Pk[rb + 4 * q];
           }
         }
-        if (live) {
 #pragma unroll
-          for (int q = 0; q < 4; ++q) acc[s] = mfma16(-a[q], b[q], acc[s]);
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+          for (int s = g; s <= gl; ++s) acc[s] = mfma16(a[s - g][q], b[s - g][q], acc[s]);
+        // blocks of column k + 1 are final: publish them for the next step
+        double *Pn = lds + ((k + 1) & 1) * pbuf;
+#pragma unroll
+        for (int s = g; s <= gl; ++s) {
+          int I, J;
+          rp_slot(s, w, I, J);
+          if (J == k + 1 && I < MB) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) Pn[(16 * I + kq + 4 * e) * RP_LD + l16] = acc[s][e];
+          }
         }
-        I = I2;
-        J = J2;
       }
     }
   }

@@ -50,9 +50,10 @@ __host__ __device__ inline int potrf_lds_doubles(int nb) {
   // instance runs it), with the pivot rows left of the panel (16 x panel
   // stride), the published pivot rows and a flag; and, up to RPOTRF_MAX, the
   // register-resident one, with two panel buffers of nb (rounded to 16) rows
-  // of 17 doubles, the published pivot rows and a flag
+  // of 17 doubles, the transposed pivot block (16 x 18), its 16 reciprocal
+  // pivots and a flag
   const int left = PANEL * panel_stride(nb) + PANEL * (PANEL + 1) + 8;
-  const int regs = 2 * ((nb + 15) / 16 * 16) * (PANEL + 1) + PANEL * (PANEL + 1) + 8;
+  const int regs = 2 * ((nb + 15) / 16 * 16) * (PANEL + 1) + PANEL * (PANEL + 2) + PANEL + 8;
   return nb <= RPOTRF_MAX && regs > left ? regs : left;
 }
 // Solve units (TRSM_L, TRSM_LT): the right-hand-side columns of the tile
