@@ -935,10 +935,10 @@ static double cost_ns(const TaskDesc &d) {
     case K_POTRF:
       if (d.m <= RPOTRF_MAX) {
         // register-resident factor: a fixed cost per 16-column step plus the
-        // trailing MFMA updates (fit to single-tile durations, 20 us at 32,
-        // 88 us at 128, 219 us at 256)
+        // trailing MFMA updates (fit to single-tile durations, 13 us at 32,
+        // 52 us at 128, 136 us at 256)
         const double mb = (m + 15.0) / 16.0;
-        return 9940.0 * mb + 14.6 * mb * mb * mb;
+        return 6670.0 * mb + 7.14 * mb * mb * mb;
       }
       // left-looking factor: latency-bound, about quadratic (444 us at 257,
       // 1.44 ms at 512)
