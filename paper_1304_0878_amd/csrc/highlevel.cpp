@@ -419,6 +419,18 @@ extern "C" int dc_potrf_batched(dc_runtime *rt, int64_t count, const dc_handle *
     Handle *p = rt->get(A[i]);
     if (p->rows == 0) continue;
     const int64_t tile = tiles[i] > 0 ? std::min<int64_t>(tiles[i], p->rows) : p->rows;
+    if (tile == p->rows) {
+      // one tile: the tasks take the registered handles themselves (no
+      // partition to create and undo)
+      const dc_handle a1[1] = {A[i]};
+      const std::vector<dc_handle> ids(a1, a1 + 1);
+      err = dcx_submit_potrf_tiles(rt, ids, 1, nullptr);
+      if (!err && B && B[i] && rt->get(B[i])->cols > 0) {
+        const std::vector<dc_handle> rows(1, B[i]);
+        err = dcx_submit_potrs_tiles(rt, ids, 1, rows, nullptr, nullptr);
+      }
+      continue;
+    }
     err = ta[i].open(rt, A[i], tile);
     if (!err) err = dcx_submit_potrf_tiles(rt, ta[i].ids, ta[i].tr, nullptr);
     if (!err && B && B[i] && rt->get(B[i])->cols > 0) {
