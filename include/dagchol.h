@@ -84,7 +84,15 @@ typedef enum { DC_F64 = 0, DC_F32 = 1, DC_BF16 = 2 } dc_dtype;
  *                                   tile (FP64, or FP32 computed in FP64 and
  *                                   rounded on store); scalar: int64 global
  *                                   row offset of D (for the info column),
- *                                   optional.
+ *                                   optional.  The executor may run an FP64
+ *                                   tile of order 257..512 as the blocked
+ *                                   factorisation of its 2 x 2 sub-blocks
+ *                                   (POTRF, TRSM, SYRK, POTRF on order <= 256;
+ *                                   same result up to rounding), where the
+ *                                   task's latency would otherwise set its
+ *                                   level's length; the graph the caller
+ *                                   submitted, its trace and its info column
+ *                                   are unchanged.
  *   DC_TRSM       (L:R, X:RW)       X <- X L^{-T}, L lower non-unit.
  *   DC_SYRK       (X:R, C:RW)       lower(C) <- lower(C) - X X^T.
  *   DC_GEMM       (X:R, Y:R, C:RW)  C <- C - X Y^T.
