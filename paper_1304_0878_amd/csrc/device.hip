@@ -505,11 +505,12 @@ __device__ __forceinline__ void run_trsm_inv(const TaskDesc &d, int unit, double
 // when step k starts: column 0 from memory, column k + 1 published by the
 // update of step k, which finishes it):
 //  (1) the first wave factors the diagonal block in registers, lane i
-//      holding row i: for each column j the pivot is taken from lane j, its
-//      reciprocal square root r is formed once (hardware estimate and two
-//      Newton steps) with l_jj = pivot * r, column j is scaled by r, and
-//      the columns right of it take a rank-one update whose column-j entries
-//      come from their lanes (readlane); the block is stored, and published
+//      holding row i (every row of 16 lanes holds the block): for each
+//      column j the pivot is taken from lane j, its reciprocal square root r
+//      is formed once (hardware estimate and two Newton steps) with
+//      l_jj = pivot * r, column j is scaled by r, and the columns right of
+//      it take a rank-one update whose column-j entries come from their
+//      lanes by a DPP row broadcast; the block is stored, and published
 //      with the reciprocals of its diagonal for step (2);
 //  (2) every thread takes one row below the diagonal block and solves it by
 //      substitution in the same column order (multiplying by the published
@@ -554,6 +555,18 @@ __device__ __forceinline__ void rp_slot(int s, int w, int &I, int &J) {
     I = first ? 8 + w : 15 - w;
     J = first ? 1 + t : 1 + t - 8 - w;
   }
+}
+
+// Value of v on lane p of each row of 16 lanes, in every lane of that row
+// (DPP row_newbcast; p a constant after unrolling: the control is encoded in
+// the instruction, hence the switch).
+__device__ __forceinline__ double row_bcast(double v, int p) {
+#define RB(q) case q: return __builtin_amdgcn_update_dpp(0.0, v, 0x150 + q, 0xf, 0xf, false)
+  switch (p) {
+    RB(0); RB(1); RB(2); RB(3); RB(4); RB(5); RB(6); RB(7);
+    RB(8); RB(9); RB(10); RB(11); RB(12); RB(13); RB(14); default: RB(15);
+  }
+#undef RB
 }
 
 // 1 / sqrt(x) for a positive normal x: the hardware estimate refined by two
@@ -677,12 +690,10 @@ __device__ __forceinline__ int run_potrf_regs(const TaskDesc &d, double *lds) {
         v[j] = i == j ? djj : v[j] * rj;
         if (i == j) rinv = rj;
         // rank-one update of the columns right of j (entries above the
-        // diagonal take garbage and are never read)
+        // diagonal take garbage and are never read); l_pj comes from lane p
+        // of the lane's row of 16, which holds the whole block
 #pragma unroll
-        for (int p = j + 1; p < PANEL; ++p) v[p] = fma(-v[j], readlane_f64(v[j], p), v[p]);
-        // keep each column's readlanes next to their uses: hoisted, they
-        // exhaust the scalar registers
-        __builtin_amdgcn_sched_barrier(0);
+        for (int p = j + 1; p < PANEL; ++p) v[p] = fma(-v[j], row_bcast(v[j], p), v[p]);
       }
       if (!f && kq == 0) {
         const int row = 16 * k + i;
