@@ -164,10 +164,18 @@ typedef struct {
   int trace;             /* nonzero: record a per-task trace at every wait */
   int executor;          /* dc_executor; 0 (DC_EXEC_LEVELS) by default;
                             DC_EXEC_QUEUE is rejected (-ENOSYS) */
+  int lookahead;         /* lookahead depth of the level executor: a task
+                            off the critical chains (the ones whose earliest
+                            and latest levels, the downward and upward ranks
+                            of Section 5.3's scheduling hints, differ) may be
+                            placed at most this many levels after its
+                            earliest one; 0 places every task at its earliest
+                            level; dc_config_default sets 48; negative:
+                            -EINVAL */
 } dc_config;
 
 /* Fills cfg with defaults (device 0, own stream, every CU, level executor,
- * 60 s watchdog). */
+ * 60 s watchdog, lookahead 48 levels). */
 void dc_config_default(dc_config *cfg);
 
 /* Creates a runtime.  Errors: -EINVAL (null pointer, unknown executor),

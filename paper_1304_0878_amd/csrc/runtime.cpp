@@ -101,6 +101,7 @@ extern "C" void dc_config_default(dc_config *cfg) {
   cfg->device = 0;
   cfg->watchdog_ms = 60000;
   cfg->executor = DC_EXEC_LEVELS;
+  cfg->lookahead = 48;
 }
 
 extern "C" int dc_init(dc_runtime **out, const dc_config *cfg) {
@@ -110,6 +111,7 @@ extern "C" int dc_init(dc_runtime **out, const dc_config *cfg) {
   if (cfg) c = *cfg; else dc_config_default(&c);
   if (c.watchdog_ms <= 0) c.watchdog_ms = 60000;
   if (c.executor != DC_EXEC_QUEUE && c.executor != DC_EXEC_LEVELS) return -EINVAL;
+  if (c.lookahead < 0) return -EINVAL;
   // The ready-queue executor's first run on the GPU did not complete (the
   // first graph of its tests was still running after 120 s, although every
   // wait of its protocol is bounded by the watchdog); until that is
@@ -977,7 +979,7 @@ static int64_t assign_levels(dc_runtime *rt, int workers, std::vector<int32_t> &
   std::vector<double> lsum(nl, 0.0), lmax(nl, 0.0);
   level.assign(nt, 0);
   const double w = std::max(1, workers);
-  const int window = 48;
+  const int window = rt->cfg.lookahead;
   // pass 1: tasks without slack (asap == alap: the critical chains) are
   // fixed first, so that the levels they occupy are known when the other
   // tasks choose theirs and can fill the CUs those chains leave idle

@@ -38,7 +38,7 @@ ERRNO = {22: "EINVAL", 2: "ENOENT", 16: "EBUSY", 12: "ENOMEM", 19: "ENODEV", 110
 class dc_config(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int), ("stream", ctypes.c_void_p), ("workers", ctypes.c_int),
                 ("watchdog_ms", ctypes.c_int64), ("trace", ctypes.c_int),
-                ("executor", ctypes.c_int)]
+                ("executor", ctypes.c_int), ("lookahead", ctypes.c_int)]
 
 
 class dc_graph_stats(ctypes.Structure):
@@ -172,7 +172,7 @@ class Runtime:
     and inspection, no execution)."""
 
     def __init__(self, device=0, stream=None, workers=0, watchdog_ms=60000, trace=False,
-                 executor=DC_EXEC_LEVELS):
+                 executor=DC_EXEC_LEVELS, lookahead=None):
         cfg = dc_config()
         _lib.dc_config_default(ctypes.byref(cfg))
         cfg.device = device
@@ -180,6 +180,8 @@ class Runtime:
         cfg.watchdog_ms = watchdog_ms
         cfg.trace = 1 if trace else 0
         cfg.executor = executor
+        if lookahead is not None:
+            cfg.lookahead = lookahead
         if device >= 0:
             import torch
             s = stream if stream is not None else torch.cuda.current_stream(device)

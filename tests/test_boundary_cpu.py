@@ -156,6 +156,20 @@ def test_error_codes(dc):
         assert e.value.code == -22  # POTRF needs FP64 or FP32 storage
 
 
+def test_lookahead_config(dc):
+    """The lookahead depth defaults to 48 levels, 0 is accepted (every task
+    at its earliest level), a negative depth is rejected."""
+    cfg = dc.dc_config()
+    dc._lib.dc_config_default(dc.ctypes.byref(cfg))
+    assert cfg.lookahead == 48
+    for depth in (0, 3):
+        with dc.Runtime(device=-1, lookahead=depth):
+            pass
+    with pytest.raises(dc.DagcholError) as e:
+        dc.Runtime(device=-1, lookahead=-1)
+    assert e.value.code == -22
+
+
 def test_ragged_partition_shapes(dc):
     with _host_rt(dc) as rt:
         a = rt.dc_matrix_register(FAKE, 1000, 1000, 1024, dc.DC_F64)
