@@ -36,7 +36,7 @@ constexpr int NT = 256;                    // threads per workgroup
 constexpr int LDS_DOUBLES = PANEL_LDS_DOUBLES;     // largest LDS need of a unit
 
 static_assert(NT == 256 && PANEL == 16 && TRSM_ROWS == 16, "stage16 maps 256 threads on 16 rows");
-static_assert(2 * TRSM_ROWS * (MAX_TILE + 2) + PANEL * (PANEL + 1) <= LDS_DOUBLES, "trsm lds");
+static_assert(2 * TRSM_ROWS * (MAX_TILE + 2) + PANEL * (PANEL + 2) + PANEL <= LDS_DOUBLES, "trsm lds");
 static_assert(PANEL * (MAX_TILE + 2) + PANEL * (PANEL + 1) + 8 <= LDS_DOUBLES, "potrf lds");
 static_assert(solve_lds_doubles(MAX_TILE) <= LDS_DOUBLES, "solve lds");
 
@@ -138,7 +138,10 @@ __device__ __forceinline__ void trsm_core(const TaskDesc &d, int unit, double *l
   const int64_t ldc = d.ldc;
   double *Xs = lds;                          // 16 x XS
   double *Lp = lds + TRSM_ROWS * XS;         // 16 x XS
-  double *Ljj = Lp + TRSM_ROWS * XS;         // 16 x 17
+  // diagonal block of the panel, transposed (l_pj in Ljt[j][p], stride 18:
+  // column j read in aligned pairs), and its reciprocal pivots
+  double *Ljt = Lp + TRSM_ROWS * XS;         // 16 x 18
+  double *Rj = Ljt + PANEL * (PANEL + 2);    // 16
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int w = tid >> 6;
@@ -173,7 +176,9 @@ __device__ __forceinline__ void trsm_core(const TaskDesc &d, int unit, double *l
     __syncthreads();
     {
       const int i = tid >> 4, j = tid & 15;
-      Ljj[i * (PANEL + 1) + j] = (i < wj && j <= i) ? Lp[i * XS + c0 + j] : 0.0;
+      const double lij = (i < wj && j <= i) ? Lp[i * XS + c0 + j] : 0.0;
+      Ljt[j * (PANEL + 2) + i] = lij;
+      if (i == j) Rj[i] = i < wj ? 1.0 / lij : 0.0;
     }
     if (TRTRI && unit == 0) {
       // lower-triangle entries of the staged rows
@@ -197,18 +202,33 @@ __device__ __forceinline__ void trsm_core(const TaskDesc &d, int unit, double *l
     }
     __syncthreads();
     if (tid < rows) {
+      // right-looking substitution with the reciprocal pivots; column j + 1
+      // of the block is read while column j is applied
       double v[PANEL];
       double *xr = Xs + tid * XS + c0;
 #pragma unroll
       for (int j = 0; j < PANEL; ++j) v[j] = j < wj ? xr[j] : 0.0;
+      double cur[PANEL], nxt[PANEL];
+      cur[0] = Rj[0];
+#pragma unroll
+      for (int p = 1; p < PANEL; ++p) cur[p] = Ljt[p];
 #pragma unroll
       for (int j = 0; j < PANEL; ++j) {
-        if (j < wj) {
-          double t = v[j];
+        if (j + 1 < PANEL) {
+          nxt[0] = Rj[j + 1];
 #pragma unroll
-          for (int p = 0; p < j; ++p) t = t - v[p] * Ljj[j * (PANEL + 1) + p];
-          v[j] = t / Ljj[j * (PANEL + 1) + j];
+          for (int p = j + 2; p < PANEL; ++p) nxt[p] = Ljt[(j + 1) * (PANEL + 2) + p];
         }
+        __builtin_amdgcn_sched_barrier(0);
+        if (j < wj) {
+          v[j] *= cur[0];
+#pragma unroll
+          for (int p = j + 1; p < PANEL; ++p) v[p] = fma(-v[j], cur[p], v[p]);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        cur[0] = nxt[0];
+#pragma unroll
+        for (int p = j + 2; p < PANEL; ++p) cur[p] = nxt[p];
       }
 #pragma unroll
       for (int j = 0; j < PANEL; ++j)
@@ -228,8 +248,8 @@ __device__ __forceinline__ void trsm_core(const TaskDesc &d, int unit, double *l
         ((gdouble *)d.c)[(int64_t)c * ldc + r0 + r] = v;
       }
     }
-    wmax = block_max(wmax, Ljj);
-    lmax = block_max(lmax, Ljj);
+    wmax = block_max(wmax, Ljt);
+    lmax = block_max(lmax, Ljt);
     if (tid == 0) {
       ((gdouble *)d.c)[(int64_t)INV_SLOT_ROW_W * ldc + 1 + unit] = wmax;
       if (unit == 0) ((gdouble *)d.c)[(int64_t)INV_SLOT_L * ldc + 2] = lmax;

@@ -40,7 +40,9 @@ __host__ __device__ inline int panel_stride(int nb) { return (nb + 31) / 32 * 32
 // LDS (doubles) each panel-kernel unit kind needs; the largest bounds the
 // panel kernel's dynamic LDS.
 __host__ __device__ inline int trsm_lds_doubles(int nb) {
-  return 2 * TRSM_ROWS * panel_stride(nb) + PANEL * (PANEL + 1);
+  // X rows and L rows (16 x panel stride each), the transposed diagonal
+  // block (16 x 18) and its 16 reciprocal pivots
+  return 2 * TRSM_ROWS * panel_stride(nb) + PANEL * (PANEL + 2) + PANEL;
 }
 // Largest tile order the register-resident POTRF takes (every 16x16 block
 // of its lower triangle held in MFMA accumulators across the four waves).
@@ -72,7 +74,7 @@ constexpr int RHS_ROWS = 16;
 // instances of the level kernel
 constexpr int LI_FULL = 0, LI_LIGHT = 1, LI_RHS = 2, LI_POTRF = 3;
 constexpr int RHS_LDS_DOUBLES = 16 * 16 * 8;
-constexpr int PANEL_LDS_DOUBLES = 2 * TRSM_ROWS * (MAX_TILE + 2) + PANEL * (PANEL + 1);
+constexpr int PANEL_LDS_DOUBLES = 2 * TRSM_ROWS * (MAX_TILE + 2) + PANEL * (PANEL + 2) + PANEL;
 
 // One task, as the executor reads it (128 bytes).
 struct TaskDesc {
