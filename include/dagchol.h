@@ -486,8 +486,11 @@ int dc_server_create(dc_server **srv, const dc_server_config *cfg);
 int dc_server_destroy(dc_server *srv);
 /* Seconds since the server was created (the clock of arrival/completion). */
 double dc_server_now(dc_server *srv);
-/* Queues a request; *id receives its id.  Errors: -EINVAL, -ENOMEM (its
- * FP64 workspace can never fit in the pool). */
+/* Queues a request; *id receives its id.  The request's A and B must hold
+ * their values when this is called: the slots run on their own streams, and
+ * nothing orders them after work the caller still has in flight on other
+ * streams (synchronise first).  Errors: -EINVAL, -ENOMEM (its FP64 workspace
+ * can never fit in the pool). */
 int dc_server_submit(dc_server *srv, const dc_request *req, int64_t *id);
 /* Never blocks: advances every request whose last step finished, admits
  * waiting requests, and copies up to cap completed results into results;

@@ -450,7 +450,9 @@ class Server:
         return _lib.dc_server_now(self._ptr)
 
     def submit(self, a, b, x, arrival=None):
-        """A (n x n), B and X (n x r): contiguous CUDA float64 tensors."""
+        """A (n x n), B and X (n x r): contiguous CUDA float64 tensors whose
+        values are complete when this is called (the server's slots run on
+        their own streams: synchronise the producing stream first)."""
         for t in (a, b, x):
             if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous():
                 raise ValueError("server tensors must be contiguous CUDA float64")
