@@ -51,10 +51,15 @@ def _serve(dc, torch_dev, systems, **kw):
     srv = dc.Server(device=0, **kw)
     try:
         xs, ids = [], []
+        reqs = []
         for a, b in systems:
             ta = torch.from_numpy(a).to(dev)
             tb = torch.from_numpy(b).to(dev)
-            tx = torch.zeros_like(tb)
+            reqs.append((ta, tb, torch.zeros_like(tb)))
+        # the inputs must be complete before they are submitted: the slots
+        # run on their own streams
+        torch.cuda.synchronize()
+        for ta, tb, tx in reqs:
             ids.append(srv.submit(ta, tb, tx))
             xs.append(tx)
         res = {d["id"]: d for d in srv.drain()}
