@@ -362,6 +362,24 @@ def test_deterministic_across_runs_and_workers(dc, torch_dev):
         assert np.array_equal(l, outs[0])
 
 
+def test_lookahead_changes_no_bit(dc, torch_dev):
+    """The lookahead depth only moves tasks between levels: the factor is
+    bit-identical for every depth, and 4096 at tile 512 also takes the
+    POTRF splitting of the late steps."""
+    outs = []
+    for n, tile in ((1536, 128), (4096, 512)):
+        a = inputs.spd_normal(n, 6, 1e-2)
+        ref = None
+        for depth in (0, 2, 48, 1000):
+            with dc.Runtime(device=0, lookahead=depth) as rt:
+                l, info, _ = _factor(dc, rt, torch_dev, a, tile)
+            assert info == 0
+            if ref is None:
+                ref = l
+                assert core.backward_error_fro(a, l) <= 1e-13
+            assert np.array_equal(l, ref), (n, depth)
+
+
 # ------------------------------------------------------------------ solve
 
 @pytest.mark.parametrize("n,r,tile", [(512, 1, 128), (700, 3, 128), (1024, 16, 256), (50, 2, 16)])
