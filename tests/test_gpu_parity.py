@@ -364,9 +364,9 @@ def test_deterministic_across_runs_and_workers(dc, torch_dev):
 
 def test_lookahead_changes_no_bit(dc, torch_dev):
     """The lookahead depth only moves tasks between levels: the factor is
-    bit-identical for every depth, and 4096 at tile 512 also takes the
-    POTRF splitting of the late steps."""
-    outs = []
+    bit-identical for every depth.  At 4096, tile 512, every diagonal factor
+    outweighs its level's other work spread over the CUs, so the POTRF
+    splitting is taken too."""
     for n, tile in ((1536, 128), (4096, 512)):
         a = inputs.spd_normal(n, 6, 1e-2)
         ref = None
