@@ -521,7 +521,7 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures the single-GPU path only: run it with --gpus 1 "
-              "(the factorisation is not sharded over several GPUs in this build)",
+              "(the library factors on one GPU; it does not shard the factorisation over several)",
               file=sys.stderr)
         sys.exit(2)
 
