@@ -416,7 +416,7 @@ def leg_batched(torch, dagchol, dev, seed, count, reps):
 
 
 def leg_serving(torch, dagchol, dev, seed, nreq, nmax, npool=96, sweep=(0.5, 0.9, 1.2),
-                mixed_min=0, sweep_requests=1000):
+                mixed_min=8192, sweep_requests=1000):
     """Open-loop serving: requests (n log-uniform in [32, nmax], 1-8
     right-hand sides, cond 10^U(2, 6)) drawn from a device-resident pool of
     `npool` matrices generated before the timed runs.  The saturated
@@ -493,6 +493,7 @@ def leg_serving(torch, dagchol, dev, seed, nreq, nmax, npool=96, sweep=(0.5, 0.9
                                         "mixed_f32": serve(dagchol.DC_F32, arr)}
     return {"requests": nreq, "n_range": [32, nmax], "pool_matrices": len(pool),
             "mixed_path": f"FP32 updates for orders >= {mixed_min}, FP64 updates below",
+            "tiles": "whole matrix up to 512, 256 below order 4096, 512 from 4096",
             "mu64_solves_per_s": mu,
             "saturated": {"fp64": sat64, "mixed_f32": sat32},
             "open_loop": opened}
@@ -514,8 +515,10 @@ def main():
     ap.add_argument("--batch-count", type=int, default=10000)
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-nmax", type=int, default=16384)
-    ap.add_argument("--mixed-min", type=int, default=0,
-                    help="serving: orders below this use FP64 updates on the mixed path")
+    ap.add_argument("--mixed-min", type=int, default=8192,
+                    help="serving: orders below this use FP64 updates on the mixed path "
+                         "(per-size runs at 512-tiles: FP32 updates ahead from 8192, level "
+                         "at 4096, behind below)")
 
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))

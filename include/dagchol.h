@@ -457,6 +457,12 @@ typedef struct {
                           costs less than the refinement steps the
                           low-precision factor needs); default 0: every
                           request uses upd */
+  int64_t tile_large;  /* tile size (<= 512) of requests of order >=
+                          large_min; default 512 */
+  int64_t large_min;   /* order from which tile_large replaces tile;
+                          default 4096 (at 4096 and above, 512-tiles
+                          served 1.2-1.5x the requests per second of
+                          256-tiles); 0: never */
 } dc_server_config;
 
 typedef struct {
@@ -477,8 +483,8 @@ typedef struct {
   double arrival, admitted, completed;   /* dc_server_now clock, seconds */
 } dc_request_result;
 
-/* Defaults: device 0, 4 slots, 64 GiB pool, tile 256, FP32 updates, tol
- * 1e-12, 30 refinement steps. */
+/* Defaults: device 0, 4 slots, 64 GiB pool, tile 256 (512 from order
+ * 4096), FP32 updates, tol 1e-12, 30 refinement steps. */
 void dc_server_config_default(dc_server_config *cfg);
 /* Errors: -EINVAL, -ENOMEM (pool allocation), -EIO. */
 int dc_server_create(dc_server **srv, const dc_server_config *cfg);

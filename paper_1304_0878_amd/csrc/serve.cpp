@@ -148,9 +148,12 @@ namespace {
 
 // Tile size of a request: orders up to whole_max are factored as one tile
 // (one POTRF task and one diagonal step per sweep): fewer levels per
-// request, but one workgroup carries the whole factorisation.
+// request, but one workgroup carries the whole factorisation; orders from
+// large_min use tile_large (larger GEMM units where the request has enough
+// tiles to fill the device anyway).
 int64_t tile_for(const dc_server_config &c, int64_t n) {
-  return (n <= c.whole_max && n >= 1) ? n : c.tile;
+  if (n <= c.whole_max && n >= 1) return n;
+  return c.large_min > 0 && n >= c.large_min ? c.tile_large : c.tile;
 }
 
 // Panel solves and the diagonal steps of the solves go through the inverses
@@ -477,6 +480,8 @@ extern "C" void dc_server_config_default(dc_server_config *c) {
   c->pool_bytes = (size_t)64 << 30;
   c->tile = 256;
   c->whole_max = dcx::MAX_TILE;
+  c->tile_large = dcx::MAX_TILE;
+  c->large_min = 4096;
   c->upd = DC_F32;
   c->tol = 1e-12;
   c->maxit = 30;
@@ -489,6 +494,7 @@ extern "C" int dc_server_create(dc_server **out, const dc_server_config *cfg) {
   if (cfg) c = *cfg; else dc_server_config_default(&c);
   if (c.slots < 1 || c.slots > 64 || c.tile < 1 || c.tile > dcx::MAX_TILE || c.pool_bytes == 0 ||
       c.whole_max < 0 || c.whole_max > dcx::MAX_TILE || c.mixed_min < 0 ||
+      c.tile_large < 1 || c.tile_large > dcx::MAX_TILE || c.large_min < 0 ||
       !(c.tol > 0) || c.maxit < 0 || (c.upd != DC_F64 && c.upd != DC_F32 && c.upd != DC_BF16))
     return -EINVAL;
   dc_server *srv = new (std::nothrow) dc_server();

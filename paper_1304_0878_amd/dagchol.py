@@ -67,7 +67,8 @@ class dc_server_config(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int), ("slots", ctypes.c_int), ("pool_bytes", ctypes.c_size_t),
                 ("tile", ctypes.c_int64), ("upd", ctypes.c_int), ("tol", ctypes.c_double),
                 ("maxit", ctypes.c_int), ("whole_max", ctypes.c_int64),
-                ("mixed_min", ctypes.c_int64)]
+                ("mixed_min", ctypes.c_int64), ("tile_large", ctypes.c_int64),
+                ("large_min", ctypes.c_int64)]
 
 
 class dc_request(ctypes.Structure):
@@ -429,7 +430,7 @@ class Server:
     submit() are kept alive here until their request completes."""
 
     def __init__(self, device=0, slots=4, pool_bytes=None, tile=256, upd=DC_F32, tol=1e-12,
-                 maxit=30, whole_max=None, mixed_min=None):
+                 maxit=30, whole_max=None, mixed_min=None, tile_large=None, large_min=None):
         cfg = dc_server_config()
         _lib.dc_server_config_default(ctypes.byref(cfg))
         cfg.device, cfg.slots, cfg.tile, cfg.upd = device, slots, tile, upd
@@ -438,6 +439,10 @@ class Server:
             cfg.whole_max = whole_max
         if mixed_min is not None:
             cfg.mixed_min = mixed_min
+        if tile_large is not None:
+            cfg.tile_large = tile_large
+        if large_min is not None:
+            cfg.large_min = large_min
         if pool_bytes is not None:
             cfg.pool_bytes = pool_bytes
         p = _P()

@@ -197,9 +197,11 @@ def test_server_config_validation(dc):
     lib.dc_server_config_default(ctypes.byref(cfg))
     assert (cfg.slots, cfg.tile, cfg.whole_max, cfg.upd, cfg.maxit) == (4, 256, 512, dc.DC_F32, 30)
     assert cfg.tol == 1e-12 and cfg.pool_bytes == 64 << 30
+    assert (cfg.tile_large, cfg.large_min, cfg.mixed_min) == (512, 4096, 0)
     for field, bad in (("whole_max", 513), ("whole_max", -1), ("tile", 0), ("tile", 513),
                        ("slots", 0), ("slots", 65), ("tol", 0.0), ("maxit", -1), ("upd", 7),
-                       ("pool_bytes", 0)):
+                       ("pool_bytes", 0), ("tile_large", 0), ("tile_large", 513),
+                       ("large_min", -1), ("mixed_min", -1)):
         c = dc.dc_server_config()
         lib.dc_server_config_default(ctypes.byref(c))
         setattr(c, field, bad)
