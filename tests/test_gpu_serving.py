@@ -96,6 +96,21 @@ def test_server_alone_equals_in_mix(dc, torch_dev):
         assert np.array_equal(x1[0], xs[i])
 
 
+def test_server_large_tile_requests(dc, torch_dev):
+    # orders from large_min are factored with tile_large, the others with
+    # tile (and up to whole_max as one tile); all share the pool and the
+    # launches, and every solution meets the oracle's
+    systems = _systems(8, 9, nmin=300, nmax=1200)
+    res, xs = _serve(dc, torch_dev, systems, slots=4, tile=128, whole_max=256,
+                     tile_large=256, large_min=600)
+    for (a, b), r, x in zip(systems, res, xs):
+        assert r["status"] == 0 and r["converged"] == 1 and r["info"] == 0, r
+        xref = mixed.reference_solution(a, b, 128)
+        assert np.abs(x - xref).max() / np.abs(xref).max() <= 1e-10, r
+    orders = [a.shape[0] for a, _ in systems]
+    assert min(orders) < 600 <= max(orders), orders
+
+
 def test_server_whole_tile_requests(dc, torch_dev):
     # orders up to whole_max (512 unless set) are factored as one tile, the
     # others with the configured tile; both kinds share the pool and the
