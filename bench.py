@@ -419,7 +419,7 @@ def leg_batched(torch, dagchol, dev, seed, count, reps):
 
 
 def leg_serving(torch, dagchol, dev, seed, nreq, nmax, npool=96, sweep=(0.5, 0.9, 1.2),
-                mixed_min=8192, sweep_requests=1000):
+                mixed_min=12288, sweep_requests=1000):
     """Open-loop serving: requests (n log-uniform in [32, nmax], 1-8
     right-hand sides, cond 10^U(2, 6)) drawn from a device-resident pool of
     `npool` matrices generated before the timed runs.  The saturated
@@ -518,10 +518,11 @@ def main():
     ap.add_argument("--batch-count", type=int, default=10000)
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-nmax", type=int, default=16384)
-    ap.add_argument("--mixed-min", type=int, default=8192,
+    ap.add_argument("--mixed-min", type=int, default=12288,
                     help="serving: orders below this use FP64 updates on the mixed path "
-                         "(per-size runs at 512-tiles: FP32 updates ahead from 8192, level "
-                         "at 4096, behind below)")
+                         "(per-size runs at 512-tiles and cond 1e4: FP32 updates ahead from "
+                         "8192; on the cond 1e2..1e6 mix, 12288 did slightly better than "
+                         "8192)")
 
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
