@@ -37,7 +37,7 @@ constexpr int LDS_DOUBLES = PANEL_LDS_DOUBLES;     // largest LDS need of a unit
 
 static_assert(NT == 256 && PANEL == 16 && TRSM_ROWS == 16, "stage16 maps 256 threads on 16 rows");
 static_assert(2 * TRSM_ROWS * (MAX_TILE + 2) + PANEL * (PANEL + 2) + PANEL <= LDS_DOUBLES, "trsm lds");
-static_assert(PANEL * (MAX_TILE + 2) + PANEL * (PANEL + 1) + 8 <= LDS_DOUBLES, "potrf lds");
+static_assert(PANEL * (MAX_TILE + 2) + PANEL * (PANEL + 2) + PANEL + 8 <= LDS_DOUBLES, "potrf lds");
 static_assert(solve_lds_doubles(MAX_TILE) <= LDS_DOUBLES, "solve lds");
 
 // Global-memory views of the tile pointers: descriptors hold generic
@@ -829,7 +829,8 @@ __device__ __forceinline__ int run_potrf_regs(const TaskDesc &d, double *lds) {
   return bad;
 }
 
-// Left-looking POTRF (any order up to MAX_TILE).
+// Left-looking POTRF (orders above RPOTRF_MAX, up to MAX_TILE; the full
+// instance runs it next to the other panel units).
 //
 // D (nb x nb, lower) = L L^T in place.  Left-looking over 16-column panels:
 // (1) D[c0:, c0:c0+16] -= D[c0:, :c0] D[c0:c0+16, :c0]^T with MFMA: the 16
@@ -999,6 +1000,210 @@ __device__ __forceinline__ int run_potrf(const TaskDesc &d, double *lds) {
 #pragma unroll
         for (int j = 0; j < PANEL; ++j)
           if (row < nb && j < wj && c0 + j <= row) D[(int64_t)row * ldd + c0 + j] = (TS)v[q][j];
+      }
+    }
+    __syncthreads();
+  }
+  return bad;
+}
+
+// Left-looking POTRF, the instance of its own (orders above RPOTRF_MAX, up
+// to MAX_TILE, in graphs without GEMM or SYRK units).
+//
+// D (nb x nb, lower) = L L^T in place.  Left-looking over 16-column panels:
+// (1) D[c0:, c0:c0+16] -= D[c0:, :c0] D[c0:c0+16, :c0]^T with MFMA: the 16
+// pivot rows are staged in LDS, each wave takes every fourth 16-row group
+// and keeps up to eight groups' accumulators, the next 16 columns of its
+// rows being loaded while the current ones are multiplied; (2) the first
+// wave factors the 16x16 diagonal block in registers as the register-
+// resident factor does (reciprocal square roots of the pivots, DPP row
+// broadcasts), and publishes it; after one barrier every thread finishes
+// its rows below the block by substitution.  Returns 0 or the 1-based local
+// column of the first non-positive or NaN pivot; the panels left of it hold
+// their final values.
+// TS: the storage type of the tile (double, or float for an FP32 factor:
+// every value is widened on load, the arithmetic is FP64, and each store
+// rounds to FP32).
+template <typename TS>
+__device__ __forceinline__ int run_potrf_ll(const TaskDesc &d, double *lds) {
+  const int nb = d.m;
+  gptr<TS> D = (gptr<TS>)d.c;
+  const int64_t ldd = d.ldc;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int w = tid >> 6;
+  const int l16 = lane & 15;
+  const int blk = l16 >> 2;
+  const int kq = lane >> 4;
+  const int n4 = lane & 3;
+  const int BS = panel_stride(nb);
+  double *Bp = lds;                          // 16 x BS: pivot rows left of the panel
+  // the factored diagonal block, transposed (l_pj in Lt[j][p], zero above
+  // the diagonal), and 1 / l_jj in Rinv[j]
+  double *Lt = Bp + PANEL * BS;
+  double *Rinv = Lt + PANEL * RP_LDT;
+  int *flag = (int *)(Rinv + PANEL);
+  constexpr int RPT = MAX_TILE / NT;         // row slots per thread
+  constexpr int GQ = MAX_TILE / PANEL / 4;   // row groups per wave
+
+  const int nj = (nb + PANEL - 1) / PANEL;
+  int bad = 0;
+  for (int J = 0; J < nj && !bad; ++J) {
+    const int c0 = PANEL * J;
+    const int wj = min(PANEL, nb - c0);
+    const int nrows = nb - c0;
+    if (c0 > 0) {
+      stage16<TS>(Bp, BS, D + (int64_t)c0 * ldd, ldd, wj, c0);
+      __syncthreads();
+      const int ngroups = (nrows + 15) / 16;
+      double acc[GQ][4];
+      double an[GQ][4];
+      gptr<const TS> ap[GQ];
+      bool aok[GQ];
+#pragma unroll
+      for (int q = 0; q < GQ; ++q) {
+        const int row = c0 + 16 * (w + 4 * q) + l16;
+        aok[q] = row < nb;
+        ap[q] = D + (int64_t)(aok[q] ? row : c0) * ldd + kq;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) acc[q][s] = 0.0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) an[q][j] = aok[q] ? ap[q][4 * j] : 0.0;
+      }
+      for (int k0 = 0; k0 < c0; k0 += 16) {
+        double ac[GQ][4];
+#pragma unroll
+        for (int q = 0; q < GQ; ++q)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) ac[q][j] = an[q][j];
+        if (k0 + 16 < c0) {
+#pragma unroll
+          for (int q = 0; q < GQ; ++q)
+            if (w + 4 * q < ngroups) {
+#pragma unroll
+              for (int j = 0; j < 4; ++j) an[q][j] = aok[q] ? ap[q][k0 + 16 + 4 * j] : 0.0;
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          double b[4];
+#pragma unroll
+          for (int s = 0; s < 4; ++s) b[s] = Bp[(4 * ((blk + s) & 3) + n4) * BS + k0 + 4 * j + kq];
+#pragma unroll
+          for (int q = 0; q < GQ; ++q)
+            if (w + 4 * q < ngroups) {
+#pragma unroll
+              for (int s = 0; s < 4; ++s) acc[q][s] = mfma44(ac[q][j], b[s], acc[q][s]);
+            }
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < GQ; ++q) {
+        if (w + 4 * q < ngroups) {
+          const int row = c0 + 16 * (w + 4 * q) + 4 * blk + kq;
+#pragma unroll
+          for (int s = 0; s < 4; ++s) {
+            const int col = 4 * ((blk + s) & 3) + n4;
+            if (row < nb && col < wj && c0 + col <= row) {
+              gptr<TS> p = D + (int64_t)row * ldd + c0 + col;
+              *p = (TS)((double)*p - acc[q][s]);
+            }
+          }
+        }
+      }
+      __syncthreads();
+    }
+    // factor of the panel: (a) the first wave factors the 16x16 diagonal
+    // block in registers, lane i holding row c0 + i (each row of 16 lanes
+    // the whole block; rows and columns past the tile padded with the
+    // identity): per column a reciprocal square root of the pivot and a
+    // rank-one update of the columns right of it through DPP row
+    // broadcasts; it stores the block and publishes it transposed with the
+    // reciprocals of its diagonal; (b) after one barrier every thread
+    // finishes its rows below the block by substitution, multiplying by the
+    // published reciprocals.
+    if (w == 0) {
+      const int i = l16;
+      double dv[PANEL];
+      {
+        const int64_t roff = (int64_t)(c0 + min(i, wj - 1)) * ldd + c0;
+#pragma unroll
+        for (int j = 0; j < PANEL; ++j) dv[j] = (double)D[roff + min(j, wj - 1)];
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int j = 0; j < PANEL; ++j)
+          dv[j] = i < wj && j < wj && j <= i ? dv[j] : (i == j ? 1.0 : 0.0);
+      }
+      double rinv = 0.0;
+      int f = 0;
+#pragma unroll
+      for (int j = 0; j < PANEL; ++j) {
+        const double piv = readlane_f64(dv[j], j);
+        if (!(piv > 0.0) && f == 0) f = j + 1;   // non-positive or NaN: uniform
+        const double rj = rsqrt_nr(piv);
+        const double djj = piv * rj;
+        dv[j] = i == j ? djj : dv[j] * rj;
+        if (i == j) rinv = rj;
+#pragma unroll
+        for (int p = j + 1; p < PANEL; ++p) dv[p] = fma(-dv[j], row_bcast(dv[j], p), dv[p]);
+      }
+      if (!f && kq == 0) {
+#pragma unroll
+        for (int j = 0; j < PANEL; ++j) {
+          const double x = j <= i ? dv[j] : 0.0;
+          Lt[j * RP_LDT + i] = x;
+          if (j <= i && i < wj) D[(int64_t)(c0 + i) * ldd + c0 + j] = (TS)x;
+        }
+        Rinv[i] = rinv;
+      }
+      if (lane == 0) *flag = f;
+    }
+    // the rows below the block (loaded while the block is factored)
+    double v[RPT][PANEL];
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      const int row = c0 + PANEL + tid + NT * q;
+      const int64_t roff = (int64_t)min(row, nb - 1) * ldd + c0;
+#pragma unroll
+      for (int j = 0; j < PANEL; ++j) v[q][j] = (double)D[roff + min(j, wj - 1)];
+    }
+    __syncthreads();
+    bad = *flag ? c0 + *flag : 0;
+    if (!bad) {
+      // column j of the block and 1 / l_jj are read while column j - 1 is
+      // applied; the columns past the tile (their l_pj zero) leave the rows
+      // unchanged
+      double cur[PANEL], nxt[PANEL];
+      cur[0] = Rinv[0];
+#pragma unroll
+      for (int p = 1; p < PANEL; ++p) cur[p] = Lt[p];
+#pragma unroll
+      for (int j = 0; j < PANEL; ++j) {
+        if (j + 1 < PANEL) {
+          nxt[0] = Rinv[j + 1];
+#pragma unroll
+          for (int p = j + 2; p < PANEL; ++p) nxt[p] = Lt[(j + 1) * RP_LDT + p];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) v[q][j] *= cur[0];
+#pragma unroll
+        for (int p = j + 1; p < PANEL; ++p)
+#pragma unroll
+          for (int q = 0; q < RPT; ++q) v[q][p] = fma(-v[q][j], cur[p], v[q][p]);
+        __builtin_amdgcn_sched_barrier(0);
+        cur[0] = nxt[0];
+#pragma unroll
+        for (int p = j + 2; p < PANEL; ++p) cur[p] = nxt[p];
+      }
+#pragma unroll
+      for (int q = 0; q < RPT; ++q) {
+        const int row = c0 + PANEL + tid + NT * q;
+        if (row < nb) {
+#pragma unroll
+          for (int j = 0; j < PANEL; ++j)
+            if (j < wj) D[(int64_t)row * ldd + c0 + j] = (TS)v[q][j];
+        }
       }
     }
     __syncthreads();
@@ -1627,14 +1832,22 @@ __device__ __forceinline__ void run_panel_unit(const TaskDesc &d, int u, double 
     }
     default: break;
   }
-  // POTRF units of order <= RPOTRF_MAX in an instance of their own, whose
-  // registers all go to the register-resident factor (the runtime sends
-  // larger ones to the full instance; one arriving here is reported as a
-  // breakdown at its first column rather than left unfactored)
-  if (MODE == LI_POTRF && kind == K_POTRF) {
-    const int bad = __builtin_amdgcn_readfirstlane(d.m) > RPOTRF_MAX ? 1
-                    : d.tc == T_F32 ? run_potrf_regs<float>(d, lds)
-                                    : run_potrf_regs<double>(d, lds);
+  // POTRF units in instances of their own: the register-resident factor up
+  // to RPOTRF_MAX (its registers go to nothing else), and above it, in
+  // graphs without GEMM or SYRK units, a left-looking one with the register-
+  // resident factor's diagonal block and reciprocal substitution (compiled
+  // into the full instance, or into one instance with the register-resident
+  // factor, it spills); a unit of the wrong order is reported as a
+  // breakdown at its first column rather than left unfactored
+  if ((MODE == LI_POTRF || MODE == LI_POTRF_LL) && kind == K_POTRF) {
+    const bool regs = __builtin_amdgcn_readfirstlane(d.m) <= RPOTRF_MAX;
+    const int bad = MODE == LI_POTRF
+                        ? (!regs ? 1
+                           : d.tc == T_F32 ? run_potrf_regs<float>(d, lds)
+                                           : run_potrf_regs<double>(d, lds))
+                        : (regs ? 1
+                           : d.tc == T_F32 ? run_potrf_ll<float>(d, lds)
+                                           : run_potrf_ll<double>(d, lds));
     if (bad && threadIdx.x == 0 && d.matrix >= 0) {
       info[d.matrix] = d.row0 + bad;
       failed[d.matrix] = 1;
@@ -1645,7 +1858,7 @@ __device__ __forceinline__ void run_panel_unit(const TaskDesc &d, int u, double 
 // Level executor: the workgroups of one level launch take the level's
 // units through an atomic counter until the list is exhausted.
 template <int MODE>
-__global__ void __launch_bounds__(NT, (MODE == LI_FULL || MODE == LI_POTRF) ? 1 : 4)
+__global__ void __launch_bounds__(NT, (MODE == LI_LIGHT || MODE == LI_RHS) ? 4 : 1)
     dc_level_kernel(LevelArgs A) {
   extern __shared__ double lds[];
   __shared__ uint64_t s_idx;
@@ -1734,7 +1947,10 @@ extern "C" int dc_selftest(void *dev_ptr, int64_t n, void *stream) {
 
 int dcx_launch_level(const LevelArgs &args, int workers, size_t lds_bytes, int inst,
                      void *stream) {
-  if (inst == LI_POTRF)
+  if (inst == LI_POTRF_LL)
+    hipLaunchKernelGGL(dc_level_kernel<LI_POTRF_LL>, dim3(workers), dim3(NT), lds_bytes,
+                       (hipStream_t)stream, args);
+  else if (inst == LI_POTRF)
     hipLaunchKernelGGL(dc_level_kernel<LI_POTRF>, dim3(workers), dim3(NT), lds_bytes,
                        (hipStream_t)stream, args);
   else if (inst == LI_LIGHT)
@@ -1769,6 +1985,7 @@ int dcx_level_setup(void) {
                         (const void *)dc_level_kernel<LI_LIGHT>,
                         (const void *)dc_level_kernel<LI_RHS>,
                         (const void *)dc_level_kernel<LI_POTRF>,
+                        (const void *)dc_level_kernel<LI_POTRF_LL>,
                         (const void *)dc_queue_panel_kernel<LI_FULL>,
                         (const void *)dc_queue_panel_kernel<LI_LIGHT>,
                         (const void *)dc_queue_panel_kernel<LI_RHS>})
@@ -1815,7 +2032,9 @@ int dcx_queue_occupancy(size_t lds_bytes, int inst, int *blocks_per_cu) {
 int dcx_level_occupancy(size_t lds_bytes, int inst, int *blocks_per_cu) {
   int nb = 0;
   hipError_t e =
-      inst == LI_POTRF ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+      inst == LI_POTRF_LL ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                             &nb, dc_level_kernel<LI_POTRF_LL>, NT, lds_bytes)
+      : inst == LI_POTRF ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
                              &nb, dc_level_kernel<LI_POTRF>, NT, lds_bytes)
       : inst == LI_LIGHT ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
                              &nb, dc_level_kernel<LI_LIGHT>, NT, lds_bytes)

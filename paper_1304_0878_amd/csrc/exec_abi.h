@@ -48,13 +48,14 @@ __host__ __device__ inline int trsm_lds_doubles(int nb) {
 // of its lower triangle held in MFMA accumulators across the four waves).
 constexpr int RPOTRF_MAX = 256;
 __host__ __device__ inline int potrf_lds_doubles(int nb) {
-  // the larger of: the left-looking POTRF (any order; the full panel-kernel
-  // instance runs it), with the pivot rows left of the panel (16 x panel
-  // stride), the published pivot rows and a flag; and, up to RPOTRF_MAX, the
-  // register-resident one, with two panel buffers of nb (rounded to 16) rows
-  // of 17 doubles, the transposed pivot block (16 x 18), its 16 reciprocal
-  // pivots and a flag
-  const int left = PANEL * panel_stride(nb) + PANEL * (PANEL + 1) + 8;
+  // above RPOTRF_MAX the left-looking POTRFs, with the pivot rows left of
+  // the panel (16 x panel stride) and either the published pivot rows (16 x
+  // 17, the full instance's) or the transposed diagonal block (16 x 18) and
+  // its 16 reciprocal pivots (the instance of its own), and a flag; up to
+  // RPOTRF_MAX the larger of that and the register-resident one, with two
+  // panel buffers of nb (rounded to 16) rows of 17 doubles, the transposed
+  // pivot block, its reciprocal pivots and a flag
+  const int left = PANEL * panel_stride(nb) + PANEL * (PANEL + 2) + PANEL + 8;
   const int regs = 2 * ((nb + 15) / 16 * 16) * (PANEL + 1) + PANEL * (PANEL + 2) + PANEL + 8;
   return nb <= RPOTRF_MAX && regs > left ? regs : left;
 }
@@ -72,7 +73,7 @@ constexpr int SOLVE_INV_ROWS = 16;
 // Rows of a right-hand-side update unit (GEMM_RHS_N, GEMM_RHS_T) and its LDS.
 constexpr int RHS_ROWS = 16;
 // instances of the level kernel
-constexpr int LI_FULL = 0, LI_LIGHT = 1, LI_RHS = 2, LI_POTRF = 3;
+constexpr int LI_FULL = 0, LI_LIGHT = 1, LI_RHS = 2, LI_POTRF = 3, LI_POTRF_LL = 4;
 constexpr int RHS_LDS_DOUBLES = 16 * 16 * 8;
 constexpr int PANEL_LDS_DOUBLES = 2 * TRSM_ROWS * (MAX_TILE + 2) + PANEL * (PANEL + 2) + PANEL;
 
@@ -123,7 +124,8 @@ struct QueueArgs {
 // Launches one level on `stream` (a hipStream_t); returns a hipError_t value.
 // inst: the instance of the level kernel (dcx::LI_FULL for any units but
 // POTRF, LI_LIGHT for residual and elementwise units only, LI_RHS for solve
-// right-hand-side updates only, LI_POTRF for POTRF units only).
+// right-hand-side updates only, LI_POTRF for POTRF units of order up to
+// RPOTRF_MAX only, LI_POTRF_LL for larger POTRF units only).
 extern "C++" int dcx_launch_level(const dcx::LevelArgs &args, int workers, size_t lds_bytes,
                                   int inst, void *stream);
 // Allows the level kernel its largest dynamic LDS size.

@@ -918,12 +918,24 @@ static size_t lds_for(const TaskDesc &d) {
 // Fewest CUs the panel kernel gets next to the GEMM kernels (measured at
 // n = 32768, tile 512: 16 beats 0, 40, 64 and 96).
 constexpr int PANEL_MIN_CUS = 16;
-// item counters per level: other panel units, the three GEMM variants, POTRF
-constexpr int NCNT = 5;
+// item counters per level: other panel units, the three GEMM variants, the
+// two POTRF instances
+constexpr int NCNT = 6;
 
-// POTRF tasks the POTRF instance of the panel kernel runs (the register-
-// resident factor; its instance has the registers for nothing else)
+// POTRF tasks the POTRF instances of the panel kernel run (each has the
+// registers for nothing else): the register-resident factor up to
+// RPOTRF_MAX; above it, in a graph without GEMM or SYRK units (a batch of
+// whole-matrix factors, a served request factored as one tile), the
+// left-looking one.  Larger POTRFs of a graph with GEMM units run in the
+// full instance, inside the launch of the level's other panel units: as a
+// third concurrent kernel of the level the faster factor made the n =
+// 32768, tile 512 factorisation 3-6% slower (its POTRFs, or the panel
+// units beside them, started late).  The choice depends on the task and
+// its graph only, so a factor's bits do not depend on its level.
 static bool regs_potrf(const TaskDesc &d) { return d.kind == K_POTRF && d.m <= RPOTRF_MAX; }
+static bool potrf_inst(const TaskDesc &d, bool graph_gemm) {
+  return regs_potrf(d) || (d.kind == K_POTRF && !graph_gemm);
+}
 
 // Rough duration (ns) of a task on one CU, for balancing levels.
 static double cost_ns(const TaskDesc &d) {
@@ -1417,7 +1429,7 @@ extern "C" int dc_flush(dc_runtime *rt) {
   // two-half kernel), then those with BF16 inputs
   auto is_g64 = [](const TaskDesc &d) { return d.ta == T_F64 || d.ta == T_F32; };
   std::vector<int64_t> pcount(nl, 0), gcount(nl, 0), lcount(nl, 0), g64count(nl, 0),
-      g32count(nl, 0), potcount(nl, 0);
+      g32count(nl, 0), potcount(nl, 0), potregs(nl, 0);
   std::vector<double> pcost(nl, 0.0), gcost(nl, 0.0), potcost(nl, 0.0);
   const bool timing = rt->ktiming;
   std::vector<double> wflops(timing ? 2 * nl : 0, 0.0), wbytes(timing ? 2 * nl : 0, 0.0);
@@ -1428,14 +1440,17 @@ extern "C" int dc_flush(dc_runtime *rt) {
     return paired(d) ? (d.nunits + 1) / 2 : d.nunits;
   };
   int64_t total_items = 0;
+  bool graph_gemm = false;
+  for (int64_t t = 0; t < nt && !graph_gemm; ++t) graph_gemm = is_gemm(rt->tasks[t].desc);
   for (int64_t t = 0; t < nt; ++t) {
     const TaskDesc &d = rt->tasks[t].desc;
     const int64_t ni = items_of(d);
     total_units += d.nunits;
     total_items += ni;
     (is_gemm(d) ? gcount : pcount)[level[t]] += ni;
-    if (regs_potrf(d)) {
+    if (potrf_inst(d, graph_gemm)) {
       potcount[level[t]] += ni;
+      if (regs_potrf(d)) potregs[level[t]] += ni;
       potcost[level[t]] += cost_ns(d);
     }
     if (paired(d)) (d.ta == T_F64 ? g64count : g32count)[level[t]] += ni;
@@ -1514,17 +1529,18 @@ extern "C" int dc_flush(dc_runtime *rt) {
   });
   // panel section of a level: POTRF units the register-resident factor
   // takes (their own kernel instance), then the rest; GEMM section: FP64-input pairs, FP32-input pairs, BF16 units
-  std::vector<int64_t> fillpot(lbegin), fillp(nl), fillg(gbegin), fill32(nl), filll(nl);
+  // POTRF items: those of the register-resident factor, then the others
+  std::vector<int64_t> fillpot(lbegin), fillpotl(nl), fillp(nl), fillg(gbegin), fill32(nl),
+      filll(nl);
   for (int64_t L = 0; L < nl; ++L) {
+    fillpotl[L] = lbegin[L] + potregs[L];
     fillp[L] = lbegin[L] + potcount[L];
     fill32[L] = gbegin[L] + g64count[L];
     filll[L] = fill32[L] + g32count[L];
   }
   std::vector<size_t> llds(nl, 16), lpot(nl, 16);
-  // POTRF units of order <= RPOTRF_MAX run the POTRF instance of the panel
-  // kernel (larger ones the full instance: a third concurrent kernel per
-  // level cost 8% at n = 32768, tile 512, with no faster factor to show for
-  // it); of the other
+  // POTRF units run the POTRF instances as potrf_inst says (the others the
+  // full instance); of the other
   // panel units, those of a level that are all residual or elementwise work
   // run the light instance, all solve right-hand-side updates the RHS
   // instance (both four workgroups per CU: these units stream from memory),
@@ -1540,12 +1556,12 @@ extern "C" int dc_flush(dc_runtime *rt) {
     desc[t] = k.desc;
     const int L = level[t];
     const bool g = is_gemm(k.desc);
-    const bool pot = regs_potrf(k.desc);
+    const bool pot = potrf_inst(k.desc, graph_gemm);
     if (pot) lpot[L] = std::max(lpot[L], lds_for(k.desc));
     else if (!g) llds[L] = std::max(llds[L], lds_for(k.desc));
     if (!g && !pot && !light_kind(k.desc.kind)) llight[L] = 0;
     if (!g && !pot && !rhs_kind(k.desc.kind)) lrhs[L] = 0;
-    int64_t &fp = pot ? fillpot[L]
+    int64_t &fp = pot ? (regs_potrf(k.desc) ? fillpot[L] : fillpotl[L])
                   : !g ? fillp[L]
                   : !is_g64(k.desc) ? filll[L]
                   : k.desc.ta == T_F64 ? fillg[L] : fill32[L];
@@ -1665,12 +1681,20 @@ extern "C" int dc_flush(dc_runtime *rt) {
       }
     }
     if (npot > 0) {
-      a.begin = lbegin[L];
-      a.count = npot;
-      a.counter = (unsigned long long *)(db + o_cnt) + NCNT * L + 4;
       hipEvent_t tb = timing ? tev(potstream) : nullptr;
-      int le = dcx_launch_level(a, std::max(1, potworkers), lpot[L], LI_POTRF, potstream);
-      if (le != 0) return fail(fail_hip((hipError_t)le, "level launch"));
+      // the register-resident factors, then the left-looking ones, on one
+      // stream, each launch with the POTRF share of the CUs
+      const int64_t nregs = potregs[L];
+      for (int v = 0; v < 2; ++v) {
+        const int64_t cnt = v == 0 ? nregs : npot - nregs;
+        if (cnt == 0) continue;
+        a.begin = lbegin[L] + (v == 0 ? 0 : nregs);
+        a.count = cnt;
+        a.counter = (unsigned long long *)(db + o_cnt) + NCNT * L + 4 + v;
+        const int wk = (int)std::min<int64_t>(cnt, std::max(1, potworkers));
+        int le = dcx_launch_level(a, wk, lpot[L], v == 0 ? LI_POTRF : LI_POTRF_LL, potstream);
+        if (le != 0) return fail(fail_hip((hipError_t)le, "level launch"));
+      }
       if (timing) {
         hipEvent_t te = tev(potstream);
         if (!tb || !te) return fail(-EIO);

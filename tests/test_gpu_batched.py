@@ -183,3 +183,65 @@ def test_batched_fp32_integer_exact(dc, rt, torch_dev):
     for (l0, x0), m, b in zip(sols, mats, rhs):
         assert np.array_equal(np.tril(m.cpu().numpy().astype(np.float64)), l0)
         assert np.array_equal(b.cpu().numpy(), x0)
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_batched_whole_tile_large_orders(dc, torch_dev, dt):
+    """Orders above 256 factored as one tile in a graph without GEMM units
+    (the left-looking POTRF's instance of its own), next to smaller ones:
+    each factor meets the oracle's bars, a matrix gives the same bits alone
+    and in the batch, and a non-SPD one reports the oracle's breakdown
+    column and leaves the others bit-identical.  The runtime is capped at
+    one CU: an FP64 POTRF is then never its level's long pole, so none is
+    split into sub-block tasks (as in a batch of thousands of matrices)."""
+    torch, dev = torch_dev
+    rt = dc.Runtime(device=0, workers=1)
+    try:
+        _whole_tile_large_orders(dc, rt, torch, dev, dt)
+    finally:
+        rt.close()
+
+
+def _whole_tile_large_orders(dc, rt, torch, dev, dt):
+    ns = [260, 100, 300, 384, 200, 450, 512, 257]
+    mats = [inputs.spd_uniform(n, 9100 + i) for i, n in enumerate(ns)]
+    rhs = [inputs.rhs(n, 2, 9200 + i) for i, n in enumerate(ns)]
+    tt = torch.float64 if dt == "f64" else torch.float32
+
+    def run(ms):
+        ta = [torch.from_numpy(m).to(dev).to(tt) for m in ms]
+        tb = [torch.from_numpy(b).to(dev) for b in rhs[:len(ms)]]
+        infos = dc.potrf_batched(rt, ta, tb, [0] * len(ms))
+        return (infos, [np.tril(t.cpu().numpy().astype(np.float64)) for t in ta],
+                [t.cpu().numpy() for t in tb])
+
+    infos, ls, xs = run(mats)
+    assert infos == [0] * len(ns)
+    U32 = 2.0 ** -24
+    for n, a, b, l, x in zip(ns, mats, rhs, ls, xs):
+        if dt == "f64":
+            assert core.backward_error_fro(a, l) <= 1e-13
+            ar, bound = a, 16 * n * U
+        else:
+            ar = a.astype(np.float32).astype(np.float64)
+            assert core.backward_error_fro(ar, l) <= 4 * n * U32
+            bound = 8 * n * U32
+        lr = np.tril(core.potrf_tiled(ar, n)[0])
+        xr = core.potrs_tiled(lr, b, n)
+        assert np.abs(x - xr).max() / np.abs(xr).max() <= bound * np.linalg.cond(ar)
+    for i in (2, 6):
+        ta = [torch.from_numpy(mats[i]).to(dev).to(tt)]
+        tb = [torch.from_numpy(rhs[i]).to(dev)]
+        assert dc.potrf_batched(rt, ta, tb, [0]) == [0]
+        assert np.array_equal(np.tril(ta[0].cpu().numpy().astype(np.float64)), ls[i])
+        assert np.array_equal(tb[0].cpu().numpy(), xs[i])
+    bad = [m.copy() for m in mats]
+    j, k = 3, 200
+    bad[j][k, k] = -1.0
+    infos2, ls2, xs2 = run(bad)
+    ref = bad[j] if dt == "f64" else bad[j].astype(np.float32).astype(np.float64)
+    assert infos2[j] == core.potrf_tiled(ref, ns[j])[1] == k + 1
+    for i in range(len(ns)):
+        if i != j:
+            assert infos2[i] == 0
+            assert np.array_equal(ls2[i], ls[i]) and np.array_equal(xs2[i], xs[i])
