@@ -1303,16 +1303,18 @@ __device__ __forceinline__ void trsm_l_pass(const TaskDesc &d, double *lds, int 
   solve_stage<CW>(Bs, Bm, ldb, nb, nb16, c0, rc);
   // this thread's entries of L for a block at row i0: row i0 + ri, columns
   // sl + 16 u left of the block and the diagonal one; those of the next
-  // block are loaded while the current block is being solved
-  double lv[MAX_TILE / 16];
-  double ldg = 0.0;
+  // block are loaded while the current block is being solved (kept in the
+  // storage type and widened where used: a conversion next to each load
+  // would make it wait for the load there)
+  TL lv[MAX_TILE / 16];
+  TL ldg = 0;
   auto lload = [&](int i0) {
     const int h = min(16, nb - i0), nu = i0 / 16;
     gptr<const TL> lr = L + (int64_t)(i0 + ri) * ldl;
 #pragma unroll
     for (int u = 0; u < MAX_TILE / 16; ++u)
-      lv[u] = (ri < h && u < nu) ? (double)lr[sl + 16 * u] : 0.0;
-    ldg = (ri < h && sl <= ri) ? (double)lr[i0 + sl] : 0.0;
+      lv[u] = (ri < h && u < nu) ? lr[sl + 16 * u] : (TL)0;
+    ldg = (ri < h && sl <= ri) ? lr[i0 + sl] : (TL)0;
   };
   lload(0);
   __syncthreads();
@@ -1327,10 +1329,10 @@ __device__ __forceinline__ void trsm_l_pass(const TaskDesc &d, double *lds, int 
       for (int u = 0; u < MAX_TILE / 16; ++u) {
         if (u < nu) {
 #pragma unroll
-          for (int c = 0; c < CW; ++c) acc[c] += lv[u] * Bs[(sl + 16 * u) * BSS + c];
+          for (int c = 0; c < CW; ++c) acc[c] += (double)lv[u] * Bs[(sl + 16 * u) * BSS + c];
         }
       }
-      Ljj[ri * 17 + sl] = ldg;
+      Ljj[ri * 17 + sl] = (double)ldg;
     }
 #pragma unroll
     for (int c = 0; c < CW; ++c) part[(ri * 16 + sl) * 16 + c] = acc[c];
@@ -1381,16 +1383,17 @@ __device__ __forceinline__ void trsm_lt_pass(const TaskDesc &d, double *lds, int
   // the later rows p = i0 + 16 + sl + 16 u (u < nu, uniform; rows past nb
   // read as zero and meet zero rows of Bs) and of the diagonal block; those
   // of the next block up are loaded while the current one is being solved
-  double lv[MAX_TILE / 16];
-  double ldg = 0.0;
+  // (in the storage type, widened where used)
+  TL lv[MAX_TILE / 16];
+  TL ldg = 0;
   auto lload = [&](int i0) {
     const int h = min(16, nb - i0), nu = (nb16 - i0 - 16) / 16;
 #pragma unroll
     for (int u = 0; u < MAX_TILE / 16; ++u) {
       const int p = i0 + 16 + sl + 16 * u;
-      lv[u] = (ci < h && u < nu && p < nb) ? (double)L[(int64_t)p * ldl + i0 + ci] : 0.0;
+      lv[u] = (ci < h && u < nu && p < nb) ? L[(int64_t)p * ldl + i0 + ci] : (TL)0;
     }
-    ldg = (sl < h && ci <= sl) ? (double)L[(int64_t)(i0 + sl) * ldl + i0 + ci] : 0.0;
+    ldg = (sl < h && ci <= sl) ? L[(int64_t)(i0 + sl) * ldl + i0 + ci] : (TL)0;
   };
   lload(16 * (nblk - 1));
   __syncthreads();
@@ -1406,12 +1409,12 @@ __device__ __forceinline__ void trsm_lt_pass(const TaskDesc &d, double *lds, int
       for (int u = 0; u < MAX_TILE / 16; ++u) {
         if (u < nu) {
 #pragma unroll
-          for (int c = 0; c < CW; ++c) acc[c] += lv[u] * Bs[(i0 + 16 + sl + 16 * u) * BSS + c];
+          for (int c = 0; c < CW; ++c) acc[c] += (double)lv[u] * Bs[(i0 + 16 + sl + 16 * u) * BSS + c];
         }
       }
     }
     // diagonal block, row sl of it: L[i0 + sl][i0 + ci]
-    Ljj[sl * 17 + ci] = ldg;
+    Ljj[sl * 17 + ci] = (double)ldg;
 #pragma unroll
     for (int c = 0; c < CW; ++c) part[(ci * 16 + sl) * 16 + c] = acc[c];
     if (bi > 0) lload(i0 - 16);
