@@ -875,7 +875,7 @@ __device__ __forceinline__ int run_potrf(const TaskDesc &d, double *lds) {
       __syncthreads();
       const int ngroups = (nrows + 15) / 16;
       double acc[GQ][4];
-      double an[GQ][4];
+      TS an[GQ][4];   // read ahead in the storage type, widened where used
       gptr<const TS> ap[GQ];
       bool aok[GQ];
 #pragma unroll
@@ -886,20 +886,20 @@ __device__ __forceinline__ int run_potrf(const TaskDesc &d, double *lds) {
 #pragma unroll
         for (int s = 0; s < 4; ++s) acc[q][s] = 0.0;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) an[q][j] = aok[q] ? ap[q][4 * j] : 0.0;
+        for (int j = 0; j < 4; ++j) an[q][j] = aok[q] ? ap[q][4 * j] : (TS)0;
       }
       for (int k0 = 0; k0 < c0; k0 += 16) {
         double ac[GQ][4];
 #pragma unroll
         for (int q = 0; q < GQ; ++q)
 #pragma unroll
-          for (int j = 0; j < 4; ++j) ac[q][j] = an[q][j];
+          for (int j = 0; j < 4; ++j) ac[q][j] = (double)an[q][j];
         if (k0 + 16 < c0) {
 #pragma unroll
           for (int q = 0; q < GQ; ++q)
             if (w + 4 * q < ngroups) {
 #pragma unroll
-              for (int j = 0; j < 4; ++j) an[q][j] = aok[q] ? ap[q][k0 + 16 + 4 * j] : 0.0;
+              for (int j = 0; j < 4; ++j) an[q][j] = aok[q] ? ap[q][k0 + 16 + 4 * j] : (TS)0;
             }
         }
 #pragma unroll
@@ -1057,7 +1057,7 @@ __device__ __forceinline__ int run_potrf_ll(const TaskDesc &d, double *lds) {
       __syncthreads();
       const int ngroups = (nrows + 15) / 16;
       double acc[GQ][4];
-      double an[GQ][4];
+      TS an[GQ][4];   // read ahead in the storage type, widened where used
       gptr<const TS> ap[GQ];
       bool aok[GQ];
 #pragma unroll
@@ -1068,20 +1068,20 @@ __device__ __forceinline__ int run_potrf_ll(const TaskDesc &d, double *lds) {
 #pragma unroll
         for (int s = 0; s < 4; ++s) acc[q][s] = 0.0;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) an[q][j] = aok[q] ? ap[q][4 * j] : 0.0;
+        for (int j = 0; j < 4; ++j) an[q][j] = aok[q] ? ap[q][4 * j] : (TS)0;
       }
       for (int k0 = 0; k0 < c0; k0 += 16) {
         double ac[GQ][4];
 #pragma unroll
         for (int q = 0; q < GQ; ++q)
 #pragma unroll
-          for (int j = 0; j < 4; ++j) ac[q][j] = an[q][j];
+          for (int j = 0; j < 4; ++j) ac[q][j] = (double)an[q][j];
         if (k0 + 16 < c0) {
 #pragma unroll
           for (int q = 0; q < GQ; ++q)
             if (w + 4 * q < ngroups) {
 #pragma unroll
-              for (int j = 0; j < 4; ++j) an[q][j] = aok[q] ? ap[q][k0 + 16 + 4 * j] : 0.0;
+              for (int j = 0; j < 4; ++j) an[q][j] = aok[q] ? ap[q][k0 + 16 + 4 * j] : (TS)0;
             }
         }
 #pragma unroll
